@@ -1,0 +1,235 @@
+"""Benchmark of the DGSEM RK-stage hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload euler3d]
+
+A step is one SSP-RK3 step (three fused dg_rk_stage launches: volume integral,
+Rusanov faces, surface lift, Jacobian scaling and the stage update) over the
+3-D Euler workload: periodic [0, 2pi]^3, 32^3 hexahedra, N = 3 (64 nodes per
+element), smooth random state, dt from CFL 0.5.  Inputs are resident in HBM
+before the timed region.  The headline is FP64; the FP32 form and the discrete
+adjoint stage are timed in the same run and reported beside it.
+
+Prints one JSON line: DOF-updates/s per RK stage (DOF = nodes x 5 variables),
+the roofline of the dominant kernel (algorithmic bytes per launch over its mean
+HIP-event duration, against 8 TB/s HBM), and the CPU oracle's throughput on a
+bounded sample of the same workload.
+"""
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import dginputs as di  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+# Algorithmic state traffic of one SSP-RK3 step: stage 1 reads U^n and writes
+# U1, stages 2 and 3 read U^n and U_k and write U_(k+1): 8 arrays over 3
+# stages, i.e. 8/3 words per DOF per stage on average.
+WORDS_PER_DOF_STAGE = 8.0 / 3.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_stages(solver, U, dt, steps, warmup):
+    """Run warmup + timed SSP-RK3 steps; returns (wall seconds of the timed
+    steps, mean per-launch kernel time in seconds from HIP events)."""
+    t1 = solver.empty()
+    t2 = solver.empty()
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        solver.ssprk3_step(U, dt, t1, t2)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3 * steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        e = ev[3 * s: 3 * s + 3]
+        e[0][0].record(stream)
+        solver.rk_stage(None, U, t1, 0.0, 1.0, dt)
+        e[0][1].record(stream)
+        e[1][0].record(stream)
+        solver.rk_stage(U, t1, t2, 0.75, 0.25, 0.25 * dt)
+        e[1][1].record(stream)
+        e[2][0].record(stream)
+        solver.rk_stage(U, t2, U, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0 * dt)
+        e[2][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern = float(np.mean([a.elapsed_time(b) for (a, b) in ev])) * 1e-3
+    return wall, kern
+
+
+def time_adjoint(solver, U, dt, steps, warmup):
+    """Adjoint of SSP-RK3 steps with stored stage states: per step three
+    dg_rk_stage_adjoint launches.  Returns (wall s per step, mean launch s)."""
+    Us = [U.clone(), solver.empty(), solver.empty()]
+    solver.rk_stage(None, Us[0], Us[1], 0.0, 1.0, dt)
+    solver.rk_stage(Us[0], Us[1], Us[2], 0.75, 0.25, 0.25 * dt)
+    lam = torch.randn_like(U)
+    mu2, mu1, acc, out = solver.empty(), solver.empty(), solver.empty(), solver.empty()
+
+    def step():
+        acc.zero_()
+        solver.rk_stage_adjoint(Us[2], lam, mu2, acc, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0 * dt)
+        solver.rk_stage_adjoint(Us[1], mu2, mu1, acc, 0.75, 0.25, 0.25 * dt)
+        solver.rk_stage_adjoint(Us[0], mu1, out, acc, 0.0, 1.0, dt, accumulate=True)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    a.record(stream)
+    for _ in range(steps):
+        step()
+    b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall / steps, a.elapsed_time(b) * 1e-3 / steps
+
+
+def cpu_baseline(p, budget_s=20.0):
+    """The CPU oracle (torch-CPU float64) timed on the host's cores on a
+    bounded sample: full RK stages on the full-size mesh until ~budget_s."""
+    from oracle.dgsem import Operator
+    from oracle.mesh import cartesian_mesh
+    from oracle.physics import Euler
+    from oracle.timestep import rk_stage, dt_cfl
+
+    cores = len(os.sched_getaffinity(0))
+    torch.set_num_threads(cores)
+    mesh = cartesian_mesh(3, p["N"], p["nel"], p["lo"], p["hi"])
+    op = Operator(mesh, Euler(3))
+    U = torch.tensor(di.random_euler(mesh.coords(), p["lo"], p["hi"]))[None]
+    dt = dt_cfl(op, U, p["cfl"])
+    nstage = 0
+    t0 = time.perf_counter()
+    Uk = U
+    coefs = ((0.0, 1.0, 1.0), (0.75, 0.25, 0.25), (1 / 3, 2 / 3, 2 / 3))
+    while True:
+        a, b, c = coefs[nstage % 3]
+        Uk = rk_stage(op, U, Uk, a, b, c * dt)
+        nstage += 1
+        if time.perf_counter() - t0 > budget_s or nstage >= 6:
+            break
+    el = time.perf_counter() - t0
+    dof = mesh.E * mesh.Np * 5
+    return dict(value=dof * nstage / el, unit="DOF-updates/s per RK stage", cores=torch.get_num_threads(),
+                kind="oracle", sample=f"{nstage} full RK stages of the 32^3 N=3 mesh ({dof} DOF), "
+                f"{el:.1f} s, torch-CPU float64, {platform.processor() or platform.machine()}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="euler3d", choices=["euler3d", "euler3d_L"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--only", choices=["f64", "f32", "adjoint"], default=None,
+                    help="time one form only (profiling runs)")
+    ap.add_argument("--calib-copy", type=int, default=0,
+                    help="instead: run a plain device copy of this many MiB 10 times (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU; multi-GPU runs are not part of it "
+              f"(--gpus {args.gpus} requested)", file=sys.stderr)
+        sys.exit(2)
+    if args.calib_copy:
+        n = args.calib_copy * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copied {args.calib_copy} MiB x 10")
+        return
+
+    from paper_2605_26388_amd import Solver
+
+    p = di.PRESETS[args.workload]
+    res = {}
+    forms = [args.only] if args.only else ["f64", "f32", "adjoint"]
+    for form in forms:
+        prec = "f32" if form == "f32" else ("f32" if form == "adjoint" else "f64")
+        s = Solver(3, p["N"], p["nel"], p["lo"], p["hi"], precision=prec)
+        X = s.node_coords().cpu().numpy()
+        U = torch.tensor(di.random_euler(X, p["lo"], p["hi"]))[None].to(s.device, s.dtype).contiguous()
+        dt = s.dt_cfl(U, p["cfl"])
+        dof = s.E * s.Np * s.nv
+        if form == "adjoint":
+            from paper_2605_26388_amd import DGError
+            st = max(1, args.steps // 2)
+            try:
+                per_step, per_step_ev = time_adjoint(s, U, dt, st, max(1, args.warmup))
+            except DGError as exc:
+                log(f"adjoint not available: {exc}")
+                res[form] = None
+                s.close()
+                continue
+            res[form] = dict(ms_per_step=per_step * 1e3, ms_per_stage=per_step_ev / 3 * 1e3, steps=st)
+            log(f"adjoint FP32: {per_step * 1e3:.3f} ms per step (3 adjoint stages)")
+        else:
+            wall, kern = time_stages(s, U, dt, args.steps, args.warmup)
+            st = s.status()
+            assert st["nonphysical"] == 0, st
+            bytes_per_launch = WORDS_PER_DOF_STAGE * (8 if prec == "f64" else 4) * dof
+            res[form] = dict(wall=wall, kern=kern, dof=dof, bytes=bytes_per_launch,
+                             value=dof * 3 * args.steps / wall, ms_per_step=wall / args.steps * 1e3)
+            log(f"{form}: {wall / args.steps * 1e3:.3f} ms/step, kernel {kern * 1e6:.1f} us/launch, "
+                f"{bytes_per_launch / kern / 1e9:.0f} GB/s algorithmic")
+        s.close()
+
+    if args.only:
+        return
+    f64 = res["f64"]
+    achieved = f64["bytes"] / f64["kern"] / 1e9
+    out = {
+        "metric": "DOF-updates/s per RK stage (FP64 vs FP32 vs adjoint), % HBM roofline",
+        "value": f64["value"],
+        "unit": "DOF-updates/s per RK stage",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": f64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: 3-D compressible Euler, periodic [0,2pi]^3, "
+                               f"{p['nel'][0]}^3 hex elements, N=3 (64 nodes/elem), smooth random state, "
+                               f"SSP-RK3 at CFL 0.5, FP64",
+                   "elements": int(np.prod(p["nel"])), "degree": 3, "dof": f64["dof"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_stage<3,3,EulerPhys<3>,double>",
+                     "kernel_us": f64["kern"] * 1e6, "bytes_per_launch": f64["bytes"]},
+        "fp32": {"value": res["f32"]["value"], "kernel_us": res["f32"]["kern"] * 1e6,
+                 "speedup_vs_fp64": f64["kern"] / res["f32"]["kern"],
+                 "roofline_frac": res["f32"]["bytes"] / res["f32"]["kern"] / 1e9 / HBM_PEAK_GBS},
+        "adjoint": None if res.get("adjoint") is None else {
+            "ms_per_step_fp32": res["adjoint"]["ms_per_step"],
+            "backward_over_forward_fp32": res["adjoint"]["ms_per_step"] / res["f32"]["ms_per_step"]},
+    }
+    if not args.no_cpu:
+        log("timing the CPU oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(dict(p, N=3))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

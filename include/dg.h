@@ -1,0 +1,194 @@
+/*
+ * dg.h -- C ABI of the MI355X DGSEM right-hand-side library (libdg.so).
+ *
+ * The library evaluates the semi-discrete operator dU/dt = L(U) of a nodal
+ * discontinuous Galerkin spectral element method (tensor-product
+ * Gauss-Lobatto-Legendre collocation) on periodic Cartesian meshes, fuses it
+ * into the Shu-Osher Runge-Kutta stage, supplies the finite-rate chemistry
+ * source and its implicit substep, and the discrete adjoint of L and of the
+ * stage.  The operations follow the paper (MARUT, arXiv 2605.26388):
+ *   - the semi-discrete system and the SSP-RK stage: SSP-RK Time
+ *     Discretization appendix;
+ *   - the volume integral and surface lift: eqs. vol_weak and surf_int of the
+ *     Kernel Architecture for Hyperbolic Terms section, with the Rusanov flux
+ *     of its Surface Fluxes paragraph and 2:1 mortars;
+ *   - BR1 viscous terms: eqs. br1_avg, tau and br1_flux (Parabolic Terms);
+ *   - the source and its implicit substep: eqs. src_reaction_rate, src_omega,
+ *     strang_split and source_residual (Source Terms).
+ *
+ * Conventions shared by every call
+ *   Layout.  Every state-like buffer (U, dUdt, adjoint variables) is
+ *     structure-of-arrays  X[b][v][e][k][j][i]  (i fastest): batch member b,
+ *     conserved variable v, element e, node (k, j, i).  Element order: coarse
+ *     cells lexicographically (x fastest); a 2:1-refined cell contributes its
+ *     four children (0,0), (1,0), (0,1), (1,1) in place.  dtype is the
+ *     context's precision: double (DG_F64) or float (DG_F32).
+ *   Variables.  Euler / Navier-Stokes: (rho, rho u, rho v[, rho w], E).
+ *     Reacting Euler (2-D): (rho_1..rho_Ns, rho u, rho v, E).
+ *   Ownership.  State buffers are device memory owned by the caller; the
+ *     library neither frees nor retains them past the call.  The context owns
+ *     its tables, constants, scratch and status counters, so a context serves
+ *     one stream at a time; calls that overlap on one context race.
+ *   Streams.  `stream` is a hipStream_t passed as void* (NULL = default
+ *     stream).  Compute calls are asynchronous on that stream; calls marked
+ *     "synchronises" wait for the stream before returning.
+ *   Errors.  Argument errors (null pointers, unsupported dim/degree/physics,
+ *     forbidden aliasing) are returned synchronously before any launch as
+ *     DG_ERR_ARG or DG_ERR_UNSUPPORTED; a failed launch returns DG_ERR_HIP.
+ *     Device-side numerical faults (non-physical state, Newton failure,
+ *     species clipping) never abort a launch: they are sticky counters read
+ *     by dg_status_read.  dg_last_error() describes the last failure of the
+ *     calling thread.
+ */
+#ifndef DG_H
+#define DG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DG_MAX_SPECIES 8
+#define DG_MAX_REACTIONS 8
+
+enum dg_status {
+  DG_OK = 0,
+  DG_ERR_ARG = 1,
+  DG_ERR_UNSUPPORTED = 2,
+  DG_ERR_HIP = 3,
+  DG_ERR_OOM = 4,
+  DG_ERR_NONPHYSICAL = 5,
+  DG_ERR_NEWTON = 6
+};
+
+enum dg_physics { DG_EULER = 0, DG_NAVIER_STOKES = 1, DG_REACTING_EULER = 2 };
+enum dg_precision { DG_F64 = 0, DG_F32 = 1 };
+
+/* Reaction mechanism (Source Terms section; finite-rate appendix).
+ * Species data per unit mass (SI); rate constants k = A T^beta exp(-Theta/T)
+ * in the units implied by kappa_c: concentrations [X_s] = kappa_c rho_s/W_s,
+ * molar rates converted back by kappa_r.  nu_f / nu_b are the reactant /
+ * product stoichiometric coefficients; third_body[r] != 0 multiplies the
+ * net rate by [M] = sum_s eff[r][s] [X_s]; reversible[r] == 0 drops the
+ * backward rate.  The struct is copied by dg_create. */
+typedef struct dg_mechanism {
+  int32_t nspecies, nreactions;
+  double W[DG_MAX_SPECIES];   /* molar mass, kg/mol */
+  double R[DG_MAX_SPECIES];   /* specific gas constant, J/(kg K) */
+  double cv[DG_MAX_SPECIES];  /* translational-rotational cv, J/(kg K) */
+  double h0[DG_MAX_SPECIES];  /* formation enthalpy, J/kg */
+  int32_t nu_f[DG_MAX_REACTIONS][DG_MAX_SPECIES];
+  int32_t nu_b[DG_MAX_REACTIONS][DG_MAX_SPECIES];
+  double A_f[DG_MAX_REACTIONS], beta_f[DG_MAX_REACTIONS], theta_f[DG_MAX_REACTIONS];
+  double A_b[DG_MAX_REACTIONS], beta_b[DG_MAX_REACTIONS], theta_b[DG_MAX_REACTIONS];
+  int32_t third_body[DG_MAX_REACTIONS];
+  int32_t reversible[DG_MAX_REACTIONS];
+  double eff[DG_MAX_REACTIONS][DG_MAX_SPECIES];
+  double kappa_c, kappa_r;
+} dg_mechanism;
+
+/* Problem description.  Periodic box [lo, hi] with nel cells per direction;
+ * 2-D only: the coarse block [patch_lo, patch_hi) is refined once (2:1),
+ * coupled through mortars (empty when patch_lo == patch_hi).
+ * Supported: dim 2 or 3; degree 1..7 (Euler), 2..4 (Navier-Stokes, 3-D),
+ * 3 (reacting, 2-D, up to DG_MAX_SPECIES species); batch >= 1.
+ * Navier-Stokes uses constant mu, non-dimensional R = 1 (T = p/rho) and
+ * k = gamma mu / (Pr (gamma - 1)).  Reacting Euler reads mech (copied). */
+typedef struct dg_desc {
+  int32_t dim, degree, physics, precision, batch;
+  int32_t nel[3];
+  double lo[3], hi[3];
+  int32_t patch_lo[2], patch_hi[2];
+  double gamma, mu, prandtl;
+  const dg_mechanism* mech;
+  int32_t newton_max_iter; /* implicit source substep, default 25 if <= 0 */
+  double newton_tol;       /* stop when max |dY| <= tol * rho, default 1e-13 */
+  int32_t device;          /* HIP device ordinal the context lives on */
+} dg_desc;
+
+/* Sticky device-side counters (dg_status_read). */
+typedef struct dg_counters {
+  int32_t nonphysical;       /* nodes seen with rho <= 0, p <= 0 or T <= 0 */
+  int32_t newton_unconverged;/* nodes whose implicit substep hit max_iter */
+  int32_t species_clips;     /* species densities clipped at 0 in Newton */
+  int32_t newton_iters_max;  /* largest iteration count of any node */
+  int64_t first_bad;         /* flat (b*E + e)*Np + node of the first
+                                non-physical node seen, -1 if none */
+} dg_counters;
+
+typedef struct dg_ctx dg_ctx;
+
+/* Build a context: mesh tables, reference-element constants, mortar
+ * operators and mechanism on the device.  Synchronous; allocates. */
+int dg_create(const dg_desc* desc, dg_ctx** out);
+int dg_destroy(dg_ctx* ctx);
+
+/* Sizes of the context: elements, nodes per element, conserved variables. */
+int dg_sizes(const dg_ctx* ctx, int64_t* nelem, int32_t* nodes_per_elem, int32_t* nvars);
+
+/* Node coordinates as double, layout xyz[d][e][node] (device, caller-owned,
+ * dim * E * Np doubles).  Asynchronous. */
+int dg_node_coords(const dg_ctx* ctx, double* xyz, void* stream);
+
+/* dUdt = L(U)  (SSP-RK appendix: the semi-discrete operator).  Volume
+ * integral (vol_weak), Rusanov interface flux, 2:1 mortars, surface lift
+ * and Jacobian scaling (surf_int); for Navier-Stokes also the BR1 viscous
+ * terms.  U and dUdt: [B][nv][E][Np]; dUdt must not alias U. */
+int dg_rhs(dg_ctx* ctx, const void* U, void* dUdt, void* stream);
+
+/* Uout = a U0 + b Uk + c_dt L(Uk)  (Shu-Osher stage, SSP-RK appendix),
+ * fused with the evaluation of L.  Uout must not alias Uk (neighbour reads);
+ * Uout == U0 is allowed.  U0 is not read when a == 0. */
+int dg_rk_stage(dg_ctx* ctx, const void* U0, const void* Uk, void* Uout,
+                double a, double b, double c_dt, void* stream);
+
+/* Chemistry source (reacting Euler only; arithmetic in double always).
+ * mode 0: out += S(U), S from eqs. src_reaction_rate / src_omega (species
+ *         rows only; momentum and energy carry no source).  out may be U.
+ * mode 1: out = U with the species densities advanced by one backward-Euler
+ *         substep of length h (eq. source_residual): Newton with one-sided
+ *         finite-difference Jacobian and Gauss-Jordan elimination per node;
+ *         momentum and energy copied unchanged.  out may be U. */
+int dg_source_chem(dg_ctx* ctx, const void* U, void* out, double h, int32_t mode, void* stream);
+
+/* Discrete adjoint of L (Euler physics, conforming meshes):
+ * lam_U = (dL/dU)^T lam_L evaluated at U, in gather form (no atomics).
+ * Subgradient convention at kinks: d max(x,y) -> x when x >= y, d|x| -> +1
+ * when x >= 0.  lam_U must not alias U or lam_L. */
+int dg_rhs_adjoint(dg_ctx* ctx, const void* U, const void* lam_L, void* lam_U, void* stream);
+
+/* Adjoint of the fused stage Uout = a U0 + b Uk + c_dt L(Uk) at Uk:
+ *   lam_k = b lam_out + c_dt (dL/dU(Uk))^T lam_out + (accumulate ? lam_0 : 0)
+ *   lam_0 = lam_0 + a lam_out                       (when lam_0 != NULL and
+ *                                                    accumulate == 0)
+ * With accumulate != 0 the accumulated lam_0 is folded into lam_k and lam_0
+ * is left unchanged (used by the first stage of a step).  lam_k must not
+ * alias Uk or lam_out; lam_0 may not alias lam_out. */
+int dg_rk_stage_adjoint(dg_ctx* ctx, const void* Uk, const void* lam_out, void* lam_k,
+                        void* lam_0, double a, double b, double c_dt, int32_t accumulate,
+                        void* stream);
+
+/* Largest stable time step from the CFL bounds (SSP-RK appendix):
+ * dt = cfl * h_min / ((2N+1) max(|u| + a)), and for Navier-Stokes
+ * min with cfl * h_min^2 / ((2N+1)^2 max(mu/rho, mu/(Pr rho))).  Reduction
+ * in double over all batch members.  Synchronises. */
+int dg_dt_cfl(dg_ctx* ctx, const void* U, double cfl, double* dt, void* stream);
+
+/* Integrals in double: out[b*(nv+1) + v] = sum_e J_e sum_i w_i U_v,i and
+ * out[b*(nv+1) + nv] = sum_e J_e sum_i w_i |m_i|^2/(2 rho_i) (kinetic
+ * energy; total density for reacting flow).  Deterministic two-level tree.
+ * out is host memory of B*(nv+1) doubles.  Synchronises. */
+int dg_integrals(dg_ctx* ctx, const void* U, double* out, void* stream);
+
+/* Read (and optionally reset) the sticky counters.  Synchronises. */
+int dg_status_read(dg_ctx* ctx, dg_counters* out, int32_t reset, void* stream);
+
+const char* dg_strerror(int code);
+const char* dg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DG_H */

@@ -1,0 +1,704 @@
+// C ABI of libdg: context creation (mesh tables, reference element, mortar
+// operators, mechanism), argument validation and dispatch to the kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dg_internal.hpp"
+
+using namespace dg;
+
+struct dg_ctx {
+  Ctx c;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(DG_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// Makes the context's device current for the scope of one call.
+struct DeviceGuard {
+  int prev = -1;
+  bool changed = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) {
+      changed = hipSetDevice(dev) == hipSuccess;
+    }
+  }
+  ~DeviceGuard() {
+    if (changed) (void)hipSetDevice(prev);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Reference element on the host (GLL nodes by Newton on P_N', weights
+// 2/(N(N+1)P_N^2), derivative matrix in barycentric form with the diagonal set
+// so that rows sum to zero).
+// ---------------------------------------------------------------------------
+void legendre(int N, double x, double& p, double& pm1) {
+  double a = 1.0, b = x;
+  if (N == 0) {
+    p = 1.0;
+    pm1 = 0.0;
+    return;
+  }
+  for (int k = 1; k < N; ++k) {
+    const double c = ((2 * k + 1) * x * b - k * a) / (k + 1);
+    a = b;
+    b = c;
+  }
+  p = b;
+  pm1 = a;
+}
+
+void gll(int N, double* xi, double* w) {
+  const double pi = 3.14159265358979323846;
+  xi[0] = -1.0;
+  xi[N] = 1.0;
+  for (int i = 1; i < N; ++i) {
+    double x = -std::cos(pi * i / N);
+    for (int it = 0; it < 100; ++it) {
+      double p, pm;
+      legendre(N, x, p, pm);
+      const double dp = N * (x * p - pm) / (x * x - 1.0);
+      const double d2p = (2.0 * x * dp - N * (N + 1) * p) / (1.0 - x * x);
+      const double dx = dp / d2p;
+      x -= dx;
+      if (std::fabs(dx) < 1e-17) break;
+    }
+    xi[i] = x;
+  }
+  for (int i = 0; i <= N / 2; ++i) {  // exact symmetry
+    const double s = 0.5 * (xi[N - i] - xi[i]);
+    xi[i] = -s;
+    xi[N - i] = s;
+  }
+  if (N % 2 == 0) xi[N / 2] = 0.0;
+  for (int i = 0; i <= N; ++i) {
+    double p, pm;
+    legendre(N, xi[i], p, pm);
+    w[i] = 2.0 / (N * (N + 1) * p * p);
+  }
+}
+
+double lagrange(const double* xi, int n, int j, double y) {
+  double r = 1.0;
+  for (int k = 0; k < n; ++k)
+    if (k != j) r *= (y - xi[k]) / (xi[j] - xi[k]);
+  return r;
+}
+
+// Gauss-Legendre nodes/weights, q points
+void gauss_legendre(int q, std::vector<double>& x, std::vector<double>& w) {
+  const double pi = 3.14159265358979323846;
+  x.resize(q);
+  w.resize(q);
+  for (int i = 0; i < q; ++i) {
+    double t = std::cos(pi * (i + 0.75) / (q + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p, pm;
+      legendre(q, t, p, pm);
+      dp = q * (t * p - pm) / (t * t - 1.0);
+      const double dt = p / dp;
+      t -= dt;
+      if (std::fabs(dt) < 1e-17) break;
+    }
+    double p, pm;
+    legendre(q, t, p, pm);
+    dp = q * (t * p - pm) / (t * t - 1.0);
+    x[i] = t;
+    w[i] = 2.0 / ((1.0 - t * t) * dp * dp);
+  }
+}
+
+// solve M X = A for X (n x n), Gaussian elimination with partial pivoting
+void solve_dense(int n, std::vector<double> M, std::vector<double>& A) {
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(M[i * n + k]) > std::fabs(M[p * n + k])) p = i;
+    if (p != k)
+      for (int j = 0; j < n; ++j) {
+        std::swap(M[k * n + j], M[p * n + j]);
+        std::swap(A[k * n + j], A[p * n + j]);
+      }
+    for (int i = k + 1; i < n; ++i) {
+      const double f = M[i * n + k] / M[k * n + k];
+      for (int j = 0; j < n; ++j) {
+        M[i * n + j] -= f * M[k * n + j];
+        A[i * n + j] -= f * A[k * n + j];
+      }
+    }
+  }
+  for (int k = n - 1; k >= 0; --k)
+    for (int j = 0; j < n; ++j) {
+      double s = A[k * n + j];
+      for (int i = k + 1; i < n; ++i) s -= M[k * n + i] * A[i * n + j];
+      A[k * n + j] = s / M[k * n + k];
+    }
+}
+
+void build_refconsts(int N, RefConsts& K) {
+  std::memset(&K, 0, sizeof(K));
+  const int n = N + 1;
+  gll(N, K.xi, K.w);
+  K.wend_inv = 1.0 / K.w[0];
+  double lam[MAXN1];
+  for (int j = 0; j < n; ++j) {
+    double p = 1.0;
+    for (int k = 0; k < n; ++k)
+      if (k != j) p *= (K.xi[j] - K.xi[k]);
+    lam[j] = 1.0 / p;
+  }
+  for (int i = 0; i < n; ++i) {
+    double diag = 0.0;
+    for (int j = 0; j < n; ++j) {
+      if (i == j) continue;
+      const double d = (lam[j] / lam[i]) / (K.xi[i] - K.xi[j]);
+      K.D[i * n + j] = d;
+      diag -= d;
+    }
+    K.D[i * n + i] = diag;
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      K.Dt[j * n + i] = K.D[i * n + j];
+      K.Df[i * n + j] = static_cast<float>(K.D[i * n + j]);
+    }
+  // mortars: forward interpolation and reverse L2 projection
+  std::vector<double> gx, gw;
+  gauss_legendre(N + 2, gx, gw);
+  std::vector<double> M(n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      for (size_t q = 0; q < gx.size(); ++q)
+        M[i * n + j] += gw[q] * lagrange(K.xi, n, i, gx[q]) * lagrange(K.xi, n, j, gx[q]);
+  for (int k = 0; k < 2; ++k) {
+    for (int i = 0; i < n; ++i) {
+      const double s = k == 0 ? 0.5 * (K.xi[i] - 1.0) : 0.5 * (K.xi[i] + 1.0);
+      for (int j = 0; j < n; ++j) K.Pf[k][i * n + j] = lagrange(K.xi, n, j, s);
+    }
+    // A = Pf^T M, then Pr = 1/2 M^{-1} A
+    std::vector<double> A(n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j)
+        for (int q = 0; q < n; ++q) A[i * n + j] += K.Pf[k][q * n + i] * M[q * n + j];
+    solve_dense(n, M, A);
+    for (int i = 0; i < n * n; ++i) K.Pr[k][i] = 0.5 * A[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Mesh: periodic box, optional 2:1-refined block (2-D)
+// ---------------------------------------------------------------------------
+struct MeshBuild {
+  std::vector<double> corner;  // [E][3]
+  std::vector<double> geo;     // [E][4]
+  std::vector<int> nbr;        // [E][2*dim]
+  std::vector<MortarRec> mortars;
+  int nrows = 0;
+  double hmin = 0.0;
+};
+
+int build_mesh(const dg_desc& d, MeshBuild& mb) {
+  const int dim = d.dim;
+  int nel[3] = {d.nel[0], d.nel[1], dim == 3 ? d.nel[2] : 1};
+  double h0[3];
+  for (int l = 0; l < 3; ++l) h0[l] = l < dim ? (d.hi[l] - d.lo[l]) / nel[l] : 1.0;
+  const bool patch = dim == 2 && (d.patch_lo[0] != d.patch_hi[0] || d.patch_lo[1] != d.patch_hi[1]);
+  auto refined = [&](int cx, int cy) {
+    return patch && cx >= d.patch_lo[0] && cx < d.patch_hi[0] && cy >= d.patch_lo[1] && cy < d.patch_hi[1];
+  };
+  // element order: coarse cells x fastest; refined cells emit 4 children
+  const long ncoarse = (long)nel[0] * nel[1] * nel[2];
+  std::vector<int> coarse_id(ncoarse, -1);
+  std::vector<int> fine_id(patch ? (size_t)4 * nel[0] * nel[1] : 0, -1);
+  const int fnx = 2 * nel[0];
+  int E = 0;
+  mb.corner.clear();
+  mb.geo.clear();
+  std::vector<int> lev, cxs, cys, czs;
+  for (int cz = 0; cz < nel[2]; ++cz)
+    for (int cy = 0; cy < nel[1]; ++cy)
+      for (int cx = 0; cx < nel[0]; ++cx) {
+        if (refined(cx, cy)) {
+          for (int fy = 0; fy < 2; ++fy)
+            for (int fx = 0; fx < 2; ++fx) {
+              const int gx = 2 * cx + fx, gy = 2 * cy + fy;
+              fine_id[(size_t)gy * fnx + gx] = E++;
+              lev.push_back(1);
+              cxs.push_back(gx);
+              cys.push_back(gy);
+              czs.push_back(0);
+            }
+        } else {
+          coarse_id[((size_t)cz * nel[1] + cy) * nel[0] + cx] = E++;
+          lev.push_back(0);
+          cxs.push_back(cx);
+          cys.push_back(cy);
+          czs.push_back(cz);
+        }
+      }
+  mb.corner.assign((size_t)E * 3, 0.0);
+  mb.geo.assign((size_t)E * 4, 0.0);
+  mb.nbr.assign((size_t)E * 2 * dim, 0);
+  mb.hmin = 1e300;
+  for (int e = 0; e < E; ++e) {
+    const double f = lev[e] ? 0.5 : 1.0;
+    const int c[3] = {cxs[e], cys[e], czs[e]};
+    double J = 1.0;
+    for (int l = 0; l < dim; ++l) {
+      const double h = h0[l] * f;
+      mb.corner[(size_t)e * 3 + l] = d.lo[l] + c[l] * h;
+      mb.geo[(size_t)e * 4 + l] = 2.0 / h;
+      J *= 0.5 * h;
+      mb.hmin = std::min(mb.hmin, h);
+    }
+    mb.geo[(size_t)e * 4 + 3] = J;
+  }
+  auto cid = [&](int x, int y, int z) {
+    x = ((x % nel[0]) + nel[0]) % nel[0];
+    y = ((y % nel[1]) + nel[1]) % nel[1];
+    z = ((z % nel[2]) + nel[2]) % nel[2];
+    return coarse_id[((size_t)z * nel[1] + y) * nel[0] + x];
+  };
+  auto fid = [&](int x, int y) {
+    const int fny = 2 * nel[1];
+    x = ((x % fnx) + fnx) % fnx;
+    y = ((y % fny) + fny) % fny;
+    return fine_id[(size_t)y * fnx + x];
+  };
+  mb.mortars.clear();
+  int rows = 0;
+  // coarse faces against refined cells create the mortar records
+  for (int e = 0; e < E; ++e) {
+    for (int l = 0; l < dim; ++l)
+      for (int side = 0; side < 2; ++side) {
+        int* slot = &mb.nbr[(size_t)e * 2 * dim + 2 * l + side];
+        const int sgn = side ? 1 : -1;
+        if (lev[e] == 0) {
+          int c[3] = {cxs[e], cys[e], czs[e]};
+          c[l] += sgn;
+          const int nb = cid(c[0], c[1], c[2]);
+          if (nb >= 0) {
+            *slot = nb;
+            continue;
+          }
+          // neighbour cell is refined: mortar, coarse side
+          MortarRec r{};
+          r.coarse = e;
+          r.l = l;
+          r.side = side;
+          const int t = 1 - l;
+          const int pc[2] = {((c[0] % nel[0]) + nel[0]) % nel[0], ((c[1] % nel[1]) + nel[1]) % nel[1]};
+          for (int s = 0; s < 2; ++s) {
+            int f[2];
+            f[l] = 2 * pc[l] + (side ? 0 : 1);
+            f[t] = 2 * (t == 0 ? cxs[e] : cys[e]) + s;
+            r.fine[s] = fid(f[0], f[1]);
+          }
+          r.row_c = rows++;
+          r.row_f[0] = rows++;
+          r.row_f[1] = rows++;
+          *slot = -(r.row_c + 1);
+          mb.mortars.push_back(r);
+        } else {
+          int f[2] = {cxs[e], cys[e]};
+          f[l] += sgn;
+          const int nb = fid(f[0], f[1]);
+          if (nb >= 0) *slot = nb;
+          else *slot = 0x7fffffff;  // filled from the mortar records below
+        }
+      }
+  }
+  for (const MortarRec& r : mb.mortars)
+    for (int s = 0; s < 2; ++s) {
+      // the fine face touching the coarse one is on the fine element's
+      // opposite side along l
+      const int fside = r.side ? 0 : 1;
+      mb.nbr[(size_t)r.fine[s] * 2 * dim + 2 * r.l + fside] = -(r.row_f[s] + 1);
+    }
+  for (size_t q = 0; q < mb.nbr.size(); ++q)
+    if (mb.nbr[q] == 0x7fffffff) return fail(DG_ERR_ARG, "mesh: unresolved fine face (refined block must be interior-consistent)");
+  mb.nrows = rows;
+  return DG_OK;
+}
+
+bool overlaps(const void* a, const void* b, size_t bytes) {
+  if (!a || !b) return false;
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  return pa < pb + bytes && pb < pa + bytes;
+}
+
+size_t state_bytes(const Ctx& c) {
+  return (size_t)c.B * c.nv * c.E * c.Np * (c.desc.precision == DG_F32 ? 4 : 8);
+}
+
+}  // namespace
+
+namespace dg {
+MeshView mesh_view(const Ctx& c) {
+  MeshView m;
+  m.E = c.E;
+  m.B = c.B;
+  m.nbr = c.d_nbr;
+  m.geo = c.d_geo;
+  m.K = c.d_K;
+  m.mortar_flux = c.d_mortar_flux;
+  m.nrows = c.nrows;
+  m.counters = c.d_counters;
+  m.first_bad = c.d_first_bad;
+  return m;
+}
+}  // namespace dg
+
+namespace {
+
+__global__ void k_reset_counters(int* cnt, unsigned long long* first_bad) {
+  if (threadIdx.x < CNT_N) cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) *first_bad = ~0ull;
+}
+
+void free_ctx(Ctx& c) {
+  void* ptrs[] = {c.d_nbr, c.d_geo, c.d_K, c.d_counters, c.d_first_bad, c.d_mortars,
+                  c.d_mortar_flux, c.d_red, c.d_red_out, c.d_face, c.d_mech, c.d_corner};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+}
+
+template <typename P>
+hipError_t upload(P** dst, const void* src, size_t bytes) {
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), bytes);
+  if (e != hipSuccess) return e;
+  if (src) return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dg_strerror(int code) {
+  switch (code) {
+    case DG_OK: return "ok";
+    case DG_ERR_ARG: return "invalid argument";
+    case DG_ERR_UNSUPPORTED: return "unsupported configuration";
+    case DG_ERR_HIP: return "HIP runtime error";
+    case DG_ERR_OOM: return "out of device memory";
+    case DG_ERR_NONPHYSICAL: return "non-physical state";
+    case DG_ERR_NEWTON: return "implicit source substep did not converge";
+  }
+  return "unknown error";
+}
+
+const char* dg_last_error(void) { return g_last_error.c_str(); }
+
+int dg_create(const dg_desc* desc, dg_ctx** out) {
+  if (!desc || !out) return fail(DG_ERR_ARG, "dg_create: null argument");
+  *out = nullptr;
+  const dg_desc& d = *desc;
+  if (d.dim != 2 && d.dim != 3) return fail(DG_ERR_UNSUPPORTED, "dim must be 2 or 3");
+  if (d.degree < 1 || d.degree > MAXN1 - 1) return fail(DG_ERR_UNSUPPORTED, "degree must be in 1..7");
+  if (d.batch < 1) return fail(DG_ERR_ARG, "batch must be >= 1");
+  if (d.precision != DG_F64 && d.precision != DG_F32) return fail(DG_ERR_ARG, "precision must be DG_F64 or DG_F32");
+  for (int l = 0; l < d.dim; ++l) {
+    if (d.nel[l] < 1) return fail(DG_ERR_ARG, "nel must be >= 1");
+    if (!(d.hi[l] > d.lo[l])) return fail(DG_ERR_ARG, "hi must exceed lo");
+  }
+  if (!(d.gamma > 1.0) && d.physics != DG_REACTING_EULER) return fail(DG_ERR_ARG, "gamma must exceed 1");
+  const bool patch = d.dim == 2 && (d.patch_lo[0] != d.patch_hi[0] || d.patch_lo[1] != d.patch_hi[1]);
+  if (patch) {
+    for (int l = 0; l < 2; ++l)
+      if (d.patch_lo[l] < 0 || d.patch_hi[l] > d.nel[l] || d.patch_lo[l] >= d.patch_hi[l])
+        return fail(DG_ERR_ARG, "patch must be a non-empty block inside the grid");
+    // a refined block that wraps the whole periodic direction has no coarse side
+    for (int l = 0; l < 2; ++l)
+      if (d.patch_hi[l] - d.patch_lo[l] >= d.nel[l]) return fail(DG_ERR_UNSUPPORTED, "patch must not span a full period");
+  }
+  switch (d.physics) {
+    case DG_EULER: break;
+    case DG_NAVIER_STOKES:
+      if (d.dim != 3 || d.degree < 2 || d.degree > 4) return fail(DG_ERR_UNSUPPORTED, "Navier-Stokes: 3-D, degree 2..4");
+      if (patch) return fail(DG_ERR_UNSUPPORTED, "Navier-Stokes on non-conforming meshes");
+      if (!(d.mu >= 0.0) || !(d.prandtl > 0.0)) return fail(DG_ERR_ARG, "mu >= 0 and prandtl > 0 required");
+      break;
+    case DG_REACTING_EULER:
+      if (d.dim != 2 || d.degree != 3) return fail(DG_ERR_UNSUPPORTED, "reacting Euler: 2-D, degree 3");
+      if (!d.mech || d.mech->nspecies != 5 || d.mech->nreactions < 1 || d.mech->nreactions > DG_MAX_REACTIONS)
+        return fail(DG_ERR_UNSUPPORTED, "reacting Euler: mechanism with 5 species and 1..8 reactions");
+      break;
+    default: return fail(DG_ERR_ARG, "unknown physics");
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(DG_ERR_HIP, "no HIP device");
+  if (d.device < 0 || d.device >= ndev) return fail(DG_ERR_ARG, "device ordinal out of range");
+
+  dg_ctx* ctx = new (std::nothrow) dg_ctx;
+  if (!ctx) return fail(DG_ERR_OOM, "host allocation");
+  Ctx& c = ctx->c;
+  c.desc = d;
+  c.desc.mech = nullptr;
+  std::memset(&c.mech, 0, sizeof(c.mech));
+  if (d.physics == DG_REACTING_EULER) c.mech = *d.mech;
+  if (c.desc.newton_max_iter <= 0) c.desc.newton_max_iter = 25;
+  if (!(c.desc.newton_tol > 0.0)) c.desc.newton_tol = 1e-13;
+  c.dim = d.dim;
+  c.N = d.degree;
+  c.n = d.degree + 1;
+  c.Np = c.dim == 2 ? c.n * c.n : c.n * c.n * c.n;
+  c.nv = d.physics == DG_REACTING_EULER ? c.mech.nspecies + c.dim + 1 : c.dim + 2;
+  c.B = d.batch;
+  c.device = d.device;
+  std::memset(&c.pc, 0, sizeof(c.pc));
+  c.pc.gamma = d.gamma;
+  c.pc.mu = d.mu;
+  c.pc.prandtl = d.prandtl;
+  for (int s = 0; s < c.mech.nspecies; ++s) {
+    c.pc.cv[s] = c.mech.cv[s];
+    c.pc.h0[s] = c.mech.h0[s];
+    c.pc.R[s] = c.mech.R[s];
+  }
+
+  MeshBuild mb;
+  int rc = build_mesh(d, mb);
+  if (rc != DG_OK) {
+    delete ctx;
+    return rc;
+  }
+  c.E = (int)(mb.corner.size() / 3);
+  c.hmin = mb.hmin;
+  c.nmortar = (int)mb.mortars.size();
+  c.nrows = mb.nrows;
+  c.h_corner = mb.corner;
+  c.h_geo = mb.geo;
+  build_refconsts(c.N, c.h_K);
+
+  DeviceGuard guard(c.device);
+  hipError_t e = hipSuccess;
+  const size_t red_cap = (size_t)std::max(c.B, 1) * 512 * 10 + 1024;
+  if ((e = upload(&c.d_nbr, mb.nbr.data(), mb.nbr.size() * sizeof(int))) != hipSuccess ||
+      (e = upload(&c.d_geo, mb.geo.data(), mb.geo.size() * sizeof(double))) != hipSuccess ||
+      (e = upload(&c.d_corner, mb.corner.data(), mb.corner.size() * sizeof(double))) != hipSuccess ||
+      (e = upload(&c.d_K, &c.h_K, sizeof(RefConsts))) != hipSuccess ||
+      (e = upload(&c.d_counters, nullptr, CNT_N * sizeof(int))) != hipSuccess ||
+      (e = upload(&c.d_first_bad, nullptr, sizeof(unsigned long long))) != hipSuccess ||
+      (e = upload(&c.d_red, nullptr, red_cap * sizeof(double))) != hipSuccess ||
+      (e = upload(&c.d_red_out, nullptr, 1024 * sizeof(double))) != hipSuccess) {
+    free_ctx(c);
+    delete ctx;
+    return e == hipErrorOutOfMemory ? fail(DG_ERR_OOM, "device allocation") : hip_fail(e, "dg_create");
+  }
+  c.red_cap = red_cap;
+  if (c.nmortar > 0) {
+    const size_t rowbytes = (size_t)c.B * c.nrows * (c.dim == 2 ? c.n : c.n * c.n) * c.nv * sizeof(double);
+    if ((e = upload(&c.d_mortars, mb.mortars.data(), mb.mortars.size() * sizeof(MortarRec))) != hipSuccess ||
+        (e = upload(&c.d_mortar_flux, nullptr, rowbytes)) != hipSuccess) {
+      free_ctx(c);
+      delete ctx;
+      return hip_fail(e, "dg_create mortars");
+    }
+  }
+  if (d.physics == DG_REACTING_EULER) {
+    if ((e = upload(&c.d_mech, &c.mech, sizeof(dg_mechanism))) != hipSuccess) {
+      free_ctx(c);
+      delete ctx;
+      return hip_fail(e, "dg_create mechanism");
+    }
+  }
+  if (d.physics == DG_NAVIER_STOKES) {
+    // BR1 face buffer: [B][E][2*dim][n^2][nv] in the context precision
+    const size_t bytes = (size_t)c.B * c.E * 2 * c.dim * c.n * c.n * c.nv * (d.precision == DG_F32 ? 4 : 8);
+    if ((e = upload(&c.d_face, nullptr, bytes)) != hipSuccess) {
+      free_ctx(c);
+      delete ctx;
+      return e == hipErrorOutOfMemory ? fail(DG_ERR_OOM, "BR1 face buffer") : hip_fail(e, "dg_create face buffer");
+    }
+  }
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, 0, c.d_counters, c.d_first_bad);
+  if ((e = hipGetLastError()) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess) {
+    free_ctx(c);
+    delete ctx;
+    return hip_fail(e, "dg_create reset");
+  }
+  *out = ctx;
+  return DG_OK;
+}
+
+int dg_destroy(dg_ctx* ctx) {
+  if (!ctx) return DG_OK;
+  DeviceGuard guard(ctx->c.device);
+  (void)hipDeviceSynchronize();
+  free_ctx(ctx->c);
+  delete ctx;
+  return DG_OK;
+}
+
+int dg_sizes(const dg_ctx* ctx, int64_t* nelem, int32_t* nodes_per_elem, int32_t* nvars) {
+  if (!ctx) return fail(DG_ERR_ARG, "dg_sizes: null context");
+  if (nelem) *nelem = ctx->c.E;
+  if (nodes_per_elem) *nodes_per_elem = ctx->c.Np;
+  if (nvars) *nvars = ctx->c.nv;
+  return DG_OK;
+}
+
+int dg_node_coords(const dg_ctx* ctx, double* xyz, void* stream) {
+  if (!ctx || !xyz) return fail(DG_ERR_ARG, "dg_node_coords: null argument");
+  const Ctx& c = ctx->c;
+  DeviceGuard guard(c.device);
+  hipError_t e = launch_coords(c, c.d_corner, xyz, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DG_OK : hip_fail(e, "dg_node_coords");
+}
+
+static int run_stage(dg_ctx* ctx, const void* U0, const void* Uk, void* out, double a, double b, double cdt,
+                     int mode, void* stream, const char* who) {
+  Ctx& c = ctx->c;
+  const size_t bytes = state_bytes(c);
+  if (overlaps(Uk, out, bytes)) return fail(DG_ERR_ARG, std::string(who) + ": output aliases the evaluated state");
+  DeviceGuard guard(c.device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  StageParams sp;
+  sp.U0 = U0;
+  sp.Uk = Uk;
+  sp.out = out;
+  sp.a = a;
+  sp.b = b;
+  sp.c = cdt;
+  sp.mode = mode;
+  hipError_t e;
+  if (c.desc.physics == DG_NAVIER_STOKES) {
+    e = launch_ns(c, sp, s);
+  } else {
+    e = launch_mortar(c, Uk, s);
+    if (e == hipSuccess) e = launch_stage(c, sp, s);
+  }
+  return e == hipSuccess ? DG_OK : hip_fail(e, who);
+}
+
+int dg_rhs(dg_ctx* ctx, const void* U, void* dUdt, void* stream) {
+  if (!ctx || !U || !dUdt) return fail(DG_ERR_ARG, "dg_rhs: null argument");
+  return run_stage(ctx, nullptr, U, dUdt, 0.0, 0.0, 1.0, 0, stream, "dg_rhs");
+}
+
+int dg_rk_stage(dg_ctx* ctx, const void* U0, const void* Uk, void* Uout, double a, double b, double c_dt,
+                void* stream) {
+  if (!ctx || !Uk || !Uout || (a != 0.0 && !U0)) return fail(DG_ERR_ARG, "dg_rk_stage: null argument");
+  if (a != 0.0 && U0 != Uout && overlaps(U0, Uout, state_bytes(ctx->c)))
+    return fail(DG_ERR_ARG, "dg_rk_stage: Uout partially overlaps U0");
+  return run_stage(ctx, U0, Uk, Uout, a, b, c_dt, 1, stream, "dg_rk_stage");
+}
+
+int dg_source_chem(dg_ctx* ctx, const void* U, void* out, double h, int32_t mode, void* stream) {
+  if (!ctx || !U || !out) return fail(DG_ERR_ARG, "dg_source_chem: null argument");
+  Ctx& c = ctx->c;
+  if (c.desc.physics != DG_REACTING_EULER) return fail(DG_ERR_UNSUPPORTED, "dg_source_chem: reacting Euler only");
+  if (mode != 0 && mode != 1) return fail(DG_ERR_ARG, "dg_source_chem: mode must be 0 or 1");
+  if (out != U && overlaps(U, out, state_bytes(c))) return fail(DG_ERR_ARG, "dg_source_chem: partial overlap");
+  DeviceGuard guard(c.device);
+  hipError_t e = launch_source(c, U, out, h, mode, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DG_OK : hip_fail(e, "dg_source_chem");
+}
+
+int dg_rhs_adjoint(dg_ctx* ctx, const void* U, const void* lam_L, void* lam_U, void* stream) {
+  if (!ctx || !U || !lam_L || !lam_U) return fail(DG_ERR_ARG, "dg_rhs_adjoint: null argument");
+  Ctx& c = ctx->c;
+  if (c.desc.physics != DG_EULER || c.nmortar > 0)
+    return fail(DG_ERR_UNSUPPORTED, "adjoint: Euler physics on conforming meshes");
+  const size_t bytes = state_bytes(c);
+  if (overlaps(lam_U, U, bytes) || overlaps(lam_U, lam_L, bytes))
+    return fail(DG_ERR_ARG, "dg_rhs_adjoint: lam_U aliases an input");
+  DeviceGuard guard(c.device);
+  hipError_t e = launch_adjoint(c, U, lam_L, lam_U, nullptr, 0.0, 0.0, 1.0, 0, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DG_OK : hip_fail(e, "dg_rhs_adjoint");
+}
+
+int dg_rk_stage_adjoint(dg_ctx* ctx, const void* Uk, const void* lam_out, void* lam_k, void* lam_0, double a,
+                        double b, double c_dt, int32_t accumulate, void* stream) {
+  if (!ctx || !Uk || !lam_out || !lam_k) return fail(DG_ERR_ARG, "dg_rk_stage_adjoint: null argument");
+  Ctx& c = ctx->c;
+  if (c.desc.physics != DG_EULER || c.nmortar > 0)
+    return fail(DG_ERR_UNSUPPORTED, "adjoint: Euler physics on conforming meshes");
+  if (accumulate && !lam_0) return fail(DG_ERR_ARG, "dg_rk_stage_adjoint: accumulate needs lam_0");
+  const size_t bytes = state_bytes(c);
+  if (overlaps(lam_k, Uk, bytes) || overlaps(lam_k, lam_out, bytes))
+    return fail(DG_ERR_ARG, "dg_rk_stage_adjoint: lam_k aliases an input");
+  if (lam_0 && (overlaps(lam_0, lam_out, bytes) || overlaps(lam_0, Uk, bytes) || overlaps(lam_0, lam_k, bytes)))
+    return fail(DG_ERR_ARG, "dg_rk_stage_adjoint: lam_0 aliases another buffer");
+  DeviceGuard guard(c.device);
+  hipError_t e = launch_adjoint(c, Uk, lam_out, lam_k, lam_0, a, b, c_dt, accumulate, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DG_OK : hip_fail(e, "dg_rk_stage_adjoint");
+}
+
+int dg_dt_cfl(dg_ctx* ctx, const void* U, double cfl, double* dt, void* stream) {
+  if (!ctx || !U || !dt) return fail(DG_ERR_ARG, "dg_dt_cfl: null argument");
+  if (!(cfl > 0.0)) return fail(DG_ERR_ARG, "dg_dt_cfl: cfl must be positive");
+  Ctx& c = ctx->c;
+  DeviceGuard guard(c.device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_lam_max(c, U, c.d_red_out, s);
+  double h[2] = {0.0, 0.0};
+  if (e == hipSuccess) e = hipMemcpyAsync(h, c.d_red_out, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "dg_dt_cfl");
+  const int p = 2 * c.N + 1;
+  double d = cfl * c.hmin / (p * h[0]);
+  if (c.desc.physics == DG_NAVIER_STOKES && c.desc.mu > 0.0) {
+    const double nu = c.desc.mu * h[1] * std::max(1.0, 1.0 / c.desc.prandtl);
+    d = std::min(d, cfl * c.hmin * c.hmin / ((double)p * p * nu));
+  }
+  *dt = d;
+  return DG_OK;
+}
+
+int dg_integrals(dg_ctx* ctx, const void* U, double* out, void* stream) {
+  if (!ctx || !U || !out) return fail(DG_ERR_ARG, "dg_integrals: null argument");
+  Ctx& c = ctx->c;
+  if (c.nv + 1 > 10) return fail(DG_ERR_UNSUPPORTED, "dg_integrals: too many variables");
+  DeviceGuard guard(c.device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_integrals(c, U, c.d_red_out, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, c.d_red_out, (size_t)c.B * (c.nv + 1) * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e == hipSuccess ? DG_OK : hip_fail(e, "dg_integrals");
+}
+
+int dg_status_read(dg_ctx* ctx, dg_counters* out, int32_t reset, void* stream) {
+  if (!ctx || !out) return fail(DG_ERR_ARG, "dg_status_read: null argument");
+  Ctx& c = ctx->c;
+  DeviceGuard guard(c.device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int cnt[CNT_N];
+  unsigned long long fb = 0;
+  hipError_t e = hipMemcpyAsync(cnt, c.d_counters, sizeof(cnt), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&fb, c.d_first_bad, sizeof(fb), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && reset) {
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, c.d_counters, c.d_first_bad);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "dg_status_read");
+  out->nonphysical = cnt[CNT_NONPHYSICAL];
+  out->newton_unconverged = cnt[CNT_NEWTON];
+  out->species_clips = cnt[CNT_CLIPS];
+  out->newton_iters_max = cnt[CNT_ITERS];
+  out->first_bad = fb == ~0ull ? -1 : (int64_t)fb;
+  return DG_OK;
+}
+
+}  // extern "C"

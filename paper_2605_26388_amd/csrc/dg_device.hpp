@@ -1,0 +1,211 @@
+// Device-side building blocks shared by the DGSEM kernels: compile-time
+// element shapes, the XCD-aware block remap, the pointwise physics (primitive
+// recovery with positivity flags, physical fluxes, wave speeds) and the
+// sticky status reporting.
+//
+// Arithmetic note: the library is compiled with floating-point contraction
+// off, so the same inline function evaluated on the same operands gives the
+// same bits at every call site.  Both elements sharing a face evaluate the
+// interface flux with the same function on the same (L, R) operands, which is
+// what makes the discrete conservation exact up to the summation order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dg_internal.hpp"
+
+namespace dg {
+
+constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+template <int DIM, int N>
+struct Shape {
+  static constexpr int n = N + 1;
+  static constexpr int NP = ipow(n, DIM);       // nodes per element
+  static constexpr int NF = ipow(n, DIM - 1);   // nodes per face
+  // elements per workgroup: fill ~256 lanes, at least one element
+  static constexpr int EPB = NP >= 256 ? 1 : 256 / NP;
+  static constexpr int NT = EPB * NP;
+  static constexpr int BS = ((NT + 63) / 64) * 64;
+};
+
+// Blocks are dispatched round-robin over the 8 XCDs (block w goes to XCD
+// w % 8).  Remap so that each XCD walks one contiguous range of element
+// blocks: face neighbours then tend to sit in the same XCD's L2.
+__device__ __forceinline__ int xcd_remap(int w, int nblocks) {
+  const int q = nblocks / 8, r = nblocks % 8;
+  const int xcd = w % 8, slot = w / 8;
+  return (xcd < r) ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+}
+
+__device__ __forceinline__ void report_nonphysical(int* counters, unsigned long long* first_bad,
+                                                   unsigned long long flat) {
+  atomicAdd(&counters[CNT_NONPHYSICAL], 1);
+  atomicMin(first_bad, flat);
+}
+
+template <typename T>
+__device__ __forceinline__ double ld(const T* p) { return static_cast<double>(*p); }
+
+// Raw buffer access to one variable plane: the base address and extent live
+// in scalar registers, each lane supplies a 32-bit element offset (no 64-bit
+// address arithmetic per lane; reads past the extent return 0).  A plane must
+// be smaller than 4 GiB, which the library checks at context creation.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)(unsigned)bytes, 0x00020000);
+}
+
+template <typename T> struct Buf;
+template <> struct Buf<double> {
+  static __device__ __forceinline__ double load(rsrc_t r, unsigned i) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, i * 8u, 0, 0));
+  }
+  static __device__ __forceinline__ void store(rsrc_t r, unsigned i, double x) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, i * 8u, 0, 0);
+  }
+};
+template <> struct Buf<float> {
+  static __device__ __forceinline__ double load(rsrc_t r, unsigned i) {
+    return static_cast<double>(__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, i * 4u, 0, 0)));
+  }
+  static __device__ __forceinline__ void store(rsrc_t r, unsigned i, double x) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, static_cast<float>(x)), r, i * 4u, 0, 0);
+  }
+};
+
+// Reciprocal and square root for the hot loops: hardware estimate refined by
+// Newton-Raphson (reciprocal) and the coupled Goldschmidt iteration (square
+// root, Markstein's formulation), accurate to about one unit in the last
+// place for the normal-range positive operands met here.  Both are plain
+// sequences of fma, so every call site rounds identically.
+__device__ __forceinline__ double frcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+__device__ __forceinline__ double fsqrt(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y;
+  double h = 0.5 * y;
+  double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  const double d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+
+// ---------------------------------------------------------------------------
+// Pointwise physics.  Thermo holds what a flux or a wave speed needs beyond U:
+// 1/rho, the pressure and the factor k with a^2 = k p / rho.
+// ---------------------------------------------------------------------------
+struct Thermo {
+  double ri;  // 1 / rho
+  double p;   // pressure
+  double k;   // a^2 = k p ri
+};
+
+// Euler / inviscid Navier-Stokes: U = (rho, m_1..m_DIM, E), ideal gas.
+template <int DIM>
+struct EulerPhys {
+  static constexpr int NV = DIM + 2;
+  static constexpr int MOM = 1;  // index of the first momentum component
+  static constexpr int NDIM = DIM;
+  // Returns false for rho <= 0 or p <= 0 (values still computed).
+  __device__ static __forceinline__ bool thermo(const double (&U)[NV], Thermo& t, const PhysConst& c) {
+    t.ri = frcp(U[0]);
+    double m2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) m2 = fma(U[1 + d], U[1 + d], m2);
+    t.p = (c.gamma - 1.0) * fma(-0.5 * m2, t.ri, U[DIM + 1]);
+    t.k = c.gamma;
+    return (U[0] > 0.0) && (t.p > 0.0);
+  }
+  // physical flux along Cartesian direction l, given u_l and p
+  __device__ static __forceinline__ void flux(const double (&U)[NV], double ul, double p, int l, double (&F)[NV]) {
+    F[0] = U[1 + l];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) F[1 + d] = U[1 + d] * ul;
+    F[1 + l] += p;
+    F[DIM + 1] = (U[DIM + 1] + p) * ul;
+  }
+};
+
+// Reacting Euler, one temperature: U = (rho_1..rho_NS, m, E).
+//   E = sum rho_s cv_s T + |m|^2/(2 rho) + sum rho_s h0_s,  p = T sum rho_s R_s,
+//   frozen sound speed a^2 = (1 + sum rho_s R_s / sum rho_s cv_s) p / rho.
+template <int DIM, int NS>
+struct ReactPhys {
+  static constexpr int NV = NS + DIM + 1;
+  static constexpr int MOM = NS;
+  static constexpr int NDIM = DIM;
+  __device__ static __forceinline__ bool thermo(const double (&U)[NV], Thermo& t, const PhysConst& c) {
+    double rho = 0.0, cv = 0.0, h0 = 0.0, Rm = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      rho += U[s];
+      cv = fma(U[s], c.cv[s], cv);
+      h0 = fma(U[s], c.h0[s], h0);
+      Rm = fma(U[s], c.R[s], Rm);
+    }
+    t.ri = frcp(rho);
+    double m2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) m2 = fma(U[NS + d], U[NS + d], m2);
+    const double cvi = frcp(cv);
+    const double T = (fma(-0.5 * m2, t.ri, U[NS + DIM]) - h0) * cvi;
+    t.p = T * Rm;
+    t.k = fma(Rm, cvi, 1.0);
+    return (rho > 0.0) && (T > 0.0) && (t.p > 0.0);
+  }
+  __device__ static __forceinline__ void flux(const double (&U)[NV], double ul, double p, int l, double (&F)[NV]) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) F[s] = U[s] * ul;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) F[NS + d] = U[NS + d] * ul;
+    F[NS + l] += p;
+    F[NS + DIM] = (U[NS + DIM] + p) * ul;
+  }
+};
+
+template <class PHYS>
+__device__ __forceinline__ double velocity(const double (&U)[PHYS::NV], const Thermo& t, int d) {
+  return U[PHYS::MOM + d] * t.ri;
+}
+
+template <class PHYS>
+__device__ __forceinline__ double sound(const Thermo& t) {
+  return fsqrt(t.k * t.p * t.ri);
+}
+
+// Rusanov (local Lax-Friedrichs) flux for the unit normal e_l between the
+// state on the -xi_l side (L) and the +xi_l side (R):
+//   F* = (F_l(UL) + F_l(UR))/2 - lam (UR - UL)/2,
+//   lam = max(|uL_l| + aL, |uR_l| + aR).
+// The caller scales by |Ja^l|: with an axis-aligned normal the flux and the
+// dissipation both scale linearly, so the unnormalised-normal flux of the
+// surface integral is |Ja^l| times this value.
+template <class PHYS>
+__device__ __forceinline__ void rusanov(const double (&UL)[PHYS::NV], const Thermo& tL, const double (&UR)[PHYS::NV],
+                                        const Thermo& tR, int l, double (&Fs)[PHYS::NV]) {
+  double FL[PHYS::NV], FR[PHYS::NV];
+  const double uL = velocity<PHYS>(UL, tL, l), uR = velocity<PHYS>(UR, tR, l);
+  PHYS::flux(UL, uL, tL.p, l, FL);
+  PHYS::flux(UR, uR, tR.p, l, FR);
+  const double cL = fabs(uL) + sound<PHYS>(tL);
+  const double cR = fabs(uR) + sound<PHYS>(tR);
+  const double hl = 0.5 * ((cL >= cR) ? cL : cR);
+#pragma unroll
+  for (int v = 0; v < PHYS::NV; ++v) Fs[v] = fma(-hl, UR[v] - UL[v], 0.5 * (FL[v] + FR[v]));
+}
+
+}  // namespace dg

@@ -1,0 +1,109 @@
+// Internal declarations of libdg: the context, the per-launch argument
+// blocks and the kernel launchers (one translation unit per kernel family).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "dg.h"
+
+namespace dg {
+
+constexpr int MAXN1 = 8;  // highest supported N + 1
+
+enum CounterIdx { CNT_NONPHYSICAL = 0, CNT_NEWTON = 1, CNT_CLIPS = 2, CNT_ITERS = 3, CNT_N = 4 };
+
+// Reference-element and mortar constants, resident in device memory.
+struct RefConsts {
+  double D[MAXN1 * MAXN1];          // D[i*n + m]: d l_m / dxi at xi_i
+  double Dt[MAXN1 * MAXN1];         // transpose, D[m*n + i]
+  float Df[MAXN1 * MAXN1];          // D rounded to float (FP32 form)
+  double w[MAXN1];                  // GLL weights
+  double xi[MAXN1];                 // GLL nodes
+  double wend_inv;                  // 1 / w_0 (= 1 / w_N)
+  double Pf[2][MAXN1 * MAXN1];      // coarse face -> mortar k  [i*n + j]
+  double Pr[2][MAXN1 * MAXN1];      // mortar k -> coarse face  [i*n + j]
+};
+
+// Pointwise physics constants passed by value with every launch.
+struct PhysConst {
+  double gamma, mu, prandtl;
+  double cv[DG_MAX_SPECIES], h0[DG_MAX_SPECIES], R[DG_MAX_SPECIES];
+};
+
+// Everything a stage/RHS launch reads besides the state buffers.
+struct MeshView {
+  int E;
+  int B;
+  const int* nbr;             // [E][2*dim]: >= 0 conforming neighbour, < 0: -(row+1)
+  const double* geo;          // [E][4]: 2/h_x, 2/h_y, 2/h_z, J
+  const RefConsts* K;
+  const double* mortar_flux;  // [B][rows][NF][nv], unit-normal interface flux
+  int nrows;
+  int* counters;
+  unsigned long long* first_bad;
+};
+
+// One 2:1 non-conforming face (2-D): coarse element, direction, side of the
+// coarse element the face lies on (1: its +l face), the two fine elements in
+// order of increasing tangential coordinate, and the flux rows of the coarse
+// face and of the two fine faces.
+struct MortarRec {
+  int coarse, l, side;
+  int fine[2];
+  int row_c, row_f[2];
+};
+
+struct StageParams {
+  const void* U0;
+  const void* Uk;
+  void* out;
+  double a, b, c;
+  int mode;  // 0: out = L(Uk);  1: out = a U0 + b Uk + c L(Uk)
+};
+
+struct Ctx {
+  dg_desc desc;
+  dg_mechanism mech;
+  int dim, N, n, Np, nv, E, B;
+  int device;
+  double hmin;
+  PhysConst pc;
+  // device buffers
+  int* d_nbr = nullptr;
+  double* d_geo = nullptr;
+  double* d_corner = nullptr;
+  RefConsts* d_K = nullptr;
+  RefConsts h_K;
+  int* d_counters = nullptr;
+  unsigned long long* d_first_bad = nullptr;
+  MortarRec* d_mortars = nullptr;
+  int nmortar = 0;
+  int nrows = 0;
+  double* d_mortar_flux = nullptr;
+  double* d_red = nullptr;       // reduction partials
+  size_t red_cap = 0;            // doubles
+  double* d_red_out = nullptr;   // final reduction results
+  void* d_face = nullptr;        // BR1 face buffer
+  void* d_mech = nullptr;        // mechanism copy on device
+  std::vector<double> h_corner;  // host copy [E][3] lower corners (coords)
+  std::vector<double> h_geo;     // host copy [E][4]
+};
+
+MeshView mesh_view(const Ctx& c);
+
+// ---- launchers (return hipError_t of the launch) ---------------------------
+hipError_t launch_stage(const Ctx& c, const StageParams& sp, hipStream_t s);
+hipError_t launch_mortar(const Ctx& c, const void* U, hipStream_t s);
+hipError_t launch_coords(const Ctx& c, const double* corner, double* xyz, hipStream_t s);
+hipError_t launch_integrals(const Ctx& c, const void* U, double* d_out, hipStream_t s);
+hipError_t launch_lam_max(const Ctx& c, const void* U, double* d_out, hipStream_t s);
+hipError_t launch_source(const Ctx& c, const void* U, void* out, double h, int mode, hipStream_t s);
+hipError_t launch_ns(const Ctx& c, const StageParams& sp, hipStream_t s);
+hipError_t launch_adjoint(const Ctx& c, const void* U, const void* lam_out, void* lam_k, void* lam_0,
+                          double a, double b, double cdt, int accumulate, hipStream_t s);
+
+}  // namespace dg

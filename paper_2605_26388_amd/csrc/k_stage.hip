@@ -1,0 +1,362 @@
+// Fused DGSEM right-hand side and Shu-Osher stage for the inviscid physics
+// (Euler, reacting Euler) on affine Cartesian elements.
+//
+// One lane per solution node, EPB elements per workgroup.  Per element:
+//   1. load U_k (coalesced: the block's elements are contiguous in every
+//      variable plane), recover primitives in double and flag non-physical
+//      nodes;
+//   2. volume integral (eq. vol_weak): contravariant fluxes (2/h_l) F_l are
+//      staged through LDS and each lane sums its three lines with the GLL
+//      derivative matrix;
+//   3. surface lift and Jacobian rescale (eq. surf_int): lanes on a face read
+//      the neighbour's matching node straight from U_k (no trace buffer, no
+//      atomics) and evaluate the Rusanov flux with the element on the -xi_l
+//      side as left state, so both elements of a face get the same bits; 2:1
+//      mortar faces take the flux from the mortar kernel's rows instead;
+//   4. write dU/dt, or the stage a U0 + b U_k + c dU/dt.
+//
+// FP32 form: states and the LDS flux operand are float, the D-sweep is a
+// float FMA chain.  Primitive recovery, flux evaluation and the face
+// corrections (F* - F) stay in double; before rounding to float the volume
+// flux has the flux of the element's first node subtracted, which leaves
+// sum_m D_im F_m unchanged (D annihilates constants) but keeps the rounding
+// error relative to the variation inside the element.
+#include <type_traits>
+
+#include "dg_device.hpp"
+
+namespace dg {
+
+template <typename T> __device__ __forceinline__ T dmat_entry(const RefConsts* K, int q);
+template <> __device__ __forceinline__ double dmat_entry<double>(const RefConsts* K, int q) { return K->D[q]; }
+template <> __device__ __forceinline__ float dmat_entry<float>(const RefConsts* K, int q) { return K->Df[q]; }
+
+template <int DIM, int N, class PHYS, typename T, bool MORTAR>
+__global__ void __launch_bounds__((Shape<DIM, N>::BS))
+k_stage(StageParams sp, MeshView mv, PhysConst pc) {
+  using S = Shape<DIM, N>;
+  constexpr int n = S::n, NP = S::NP, EPB = S::EPB, NV = PHYS::NV, MOM = PHYS::MOM;
+  constexpr bool F32 = std::is_same<T, float>::value;
+
+  __shared__ T sF[DIM][NV][EPB * NP];
+  __shared__ T sD[n * n];
+  __shared__ double sRef[F32 ? EPB : 1][DIM][NV];
+
+  const int tid = threadIdx.x;
+  for (int q = tid; q < n * n; q += S::BS) sD[q] = dmat_entry<T>(mv.K, q);
+
+  const int E = mv.E;
+  const int nEB = (E + EPB - 1) / EPB;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = blk / nEB;
+  const int eb = blk - b * nEB;
+  const int el = tid / NP;
+  const int node = tid - el * NP;
+  const int e = eb * EPB + el;
+  const bool active = (tid < S::NT) && (e < E);
+  const int ec = active ? e : 0;  // clamped for address arithmetic only
+
+  int ii[3];
+  ii[0] = node % n;
+  ii[1] = (node / n) % n;
+  ii[2] = node / (n * n);
+  const int stride[3] = {1, n, n * n};
+
+  // One buffer descriptor per variable plane (scalar registers); per-lane
+  // element offsets are 32-bit.
+  const size_t plane = (size_t)E * NP;
+  const size_t pbytes = plane * sizeof(T);
+  const T* Ub = static_cast<const T*>(sp.Uk) + (size_t)b * NV * plane;
+  rsrc_t rU[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) rU[v] = make_rsrc(Ub + v * plane, pbytes);
+  const unsigned off = (unsigned)(ec * NP + node);
+
+  double u[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u[v] = Buf<T>::load(rU[v], off);
+
+  // Face lanes prefetch the neighbour's matching node for every face they lie on.
+  int side[DIM], nbe[DIM];
+  double un[DIM][NV];
+  const int* nb = mv.nbr + (size_t)ec * 2 * DIM;
+#pragma unroll
+  for (int l = 0; l < DIM; ++l) {
+    side[l] = (ii[l] == 0) ? 0 : ((ii[l] == N) ? 1 : -1);
+    nbe[l] = (active && side[l] >= 0) ? nb[2 * l + side[l]] : -1;
+    if (nbe[l] >= 0) {
+      const unsigned noff = (unsigned)(nbe[l] * NP + node + (side[l] ? -N : N) * stride[l]);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) un[l][v] = Buf<T>::load(rU[v], noff);
+    }
+  }
+  // stage input U0, fetched early as well
+  const bool use_u0 = (sp.mode != 0) && (sp.a != 0.0);
+  double u0[NV];
+  if (use_u0 && active) {
+    const T* U0b = static_cast<const T*>(sp.U0) + (size_t)b * NV * plane;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u0[v] = Buf<T>::load(make_rsrc(U0b + v * plane, pbytes), off);
+  } else {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u0[v] = 0.0;
+  }
+
+  Thermo th;
+  const bool ok = PHYS::thermo(u, th, pc);
+  if (active && !ok)
+    report_nonphysical(mv.counters, mv.first_bad, ((unsigned long long)b * E + e) * NP + node);
+  double vel[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) vel[d] = u[MOM + d] * th.ri;
+
+  // ---- stage physical fluxes in LDS -------------------------------------
+  if constexpr (F32) {
+    if (tid < S::NT && node == 0) {
+#pragma unroll
+      for (int l = 0; l < DIM; ++l) {
+        double F[NV];
+        PHYS::flux(u, vel[l], th.p, l, F);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sRef[el][l][v] = F[v];
+      }
+    }
+    __syncthreads();
+  }
+  if (tid < S::NT) {
+#pragma unroll
+    for (int l = 0; l < DIM; ++l) {
+      double F[NV];
+      PHYS::flux(u, vel[l], th.p, l, F);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        if constexpr (F32) sF[l][v][tid] = static_cast<float>(F[v] - sRef[el][l][v]);
+        else sF[l][v][tid] = F[v];
+      }
+    }
+  }
+  __syncthreads();
+
+  double g[DIM];
+#pragma unroll
+  for (int l = 0; l < DIM; ++l) g[l] = mv.geo[(size_t)ec * 4 + l];
+
+  // ---- volume integral: -sum_l (2/h_l) sum_m D_im F_l,m ----------------
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  if (tid < S::NT) {
+#pragma unroll
+    for (int l = 0; l < DIM; ++l) {
+      const int il = ii[l];
+      const int st = stride[l];
+      const int base = tid - il * st;
+      T drow[n];
+#pragma unroll
+      for (int m = 0; m < n; ++m) drow[m] = sD[il * n + m] * static_cast<T>(-g[l]);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        T s = 0;
+#pragma unroll
+        for (int m = 0; m < n; ++m) s = fma(drow[m], sF[l][v][base + m * st], s);
+        acc[v] += static_cast<double>(s);
+      }
+    }
+  }
+
+  // ---- surface lift (eq. surf_int) ----------------------------------------
+  bool on_face = false;
+#pragma unroll
+  for (int l = 0; l < DIM; ++l) on_face |= side[l] >= 0;
+  if (active && on_face) {
+    const double aown = sound<PHYS>(th);
+    const double winv = mv.K->wend_inv;
+#pragma unroll
+    for (int l = 0; l < DIM; ++l) {
+      if (side[l] < 0) continue;
+      double Fo[NV], Fs[NV];
+      PHYS::flux(u, vel[l], th.p, l, Fo);
+      if (!MORTAR || nbe[l] >= 0) {
+        // Rusanov flux with the element on the -xi_l side as left state.
+        // Written in own/neighbour form: the average is symmetric and the
+        // jump term changes sign with the side, both exactly, so the two
+        // elements of a face obtain the same bits.
+        Thermo tn;
+        PHYS::thermo(un[l], tn, pc);
+        const double vn = un[l][MOM + l] * tn.ri;
+        double Fn[NV];
+        PHYS::flux(un[l], vn, tn.p, l, Fn);
+        const double co = fabs(vel[l]) + aown;
+        const double cn = fabs(vn) + sound<PHYS>(tn);
+        const double hl = 0.5 * (co >= cn ? co : cn);
+        const double hs = side[l] ? hl : -hl;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Fs[v] = fma(-hs, un[l][v] - u[v], 0.5 * (Fo[v] + Fn[v]));
+      } else {
+        const int row = -nbe[l] - 1;
+        const int t = (DIM == 2) ? ii[1 - l] : 0;
+        const double* src = mv.mortar_flux + (((size_t)b * mv.nrows + row) * S::NF + t) * NV;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Fs[v] = src[v];
+      }
+      const double sc = (side[l] ? -g[l] : g[l]) * winv;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[v] = fma(sc, Fs[v] - Fo[v], acc[v]);
+    }
+  }
+
+  // ---- output ----------------------------------------------------------------
+  if (active) {
+    T* outb = static_cast<T*>(sp.out) + (size_t)b * NV * plane;
+    if (sp.mode == 0) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Buf<T>::store(make_rsrc(outb + v * plane, pbytes), off, acc[v]);
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double r = fma(sp.c, acc[v], sp.b * u[v]);
+        if (use_u0) r = fma(sp.a, u0[v], r);
+        Buf<T>::store(make_rsrc(outb + v * plane, pbytes), off, r);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 2:1 mortar fluxes (2-D): one workgroup per non-conforming face and batch
+// member.  Lane (k, q) interpolates the coarse trace onto node q of mortar k,
+// evaluates the Rusanov flux against fine element k (unit normal: fine and
+// coarse lifts both use their own 2/h), and writes the fine row; the coarse
+// row is the L2 projection sum_k Pr_k F*_k (the coarse/mortar length ratio 2
+// cancels against the ratio of the contravariant normals).
+// ---------------------------------------------------------------------------
+template <int N, class PHYS, typename T>
+__global__ void __launch_bounds__(64)
+k_mortar(const MortarRec* recs, const T* U, MeshView mv, PhysConst pc) {
+  constexpr int n = N + 1, NP = n * n, NV = PHYS::NV;
+  __shared__ double sFs[2][n][NV];
+  const MortarRec r = recs[blockIdx.x];
+  const int b = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int E = mv.E;
+  const size_t plane = (size_t)E * NP;
+  const size_t bofs = (size_t)b * NV * plane;
+  const int l = r.l;
+  auto nodeidx = [&](int along, int tang) { return l == 0 ? along + n * tang : tang + n * along; };
+  const int cend = r.side ? N : 0;
+  const int fend = r.side ? 0 : N;
+  if (tid < 2 * n) {
+    const int k = tid / n, q = tid - (tid / n) * n;
+    double uc[NV], uf[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < n; ++j)
+        s = fma(mv.K->Pf[k][q * n + j], ld(U + bofs + v * plane + (size_t)r.coarse * NP + nodeidx(cend, j)), s);
+      uc[v] = s;
+      uf[v] = ld(U + bofs + v * plane + (size_t)r.fine[k] * NP + nodeidx(fend, q));
+    }
+    Thermo tc, tf;
+    PHYS::thermo(uc, tc, pc);
+    PHYS::thermo(uf, tf, pc);
+    double Fs[NV];
+    if (r.side == 1) rusanov<PHYS>(uc, tc, uf, tf, l, Fs);   // coarse on the -xi_l side
+    else rusanov<PHYS>(uf, tf, uc, tc, l, Fs);
+    double* dst = const_cast<double*>(mv.mortar_flux) + (((size_t)b * mv.nrows + r.row_f[k]) * n + q) * NV;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      dst[v] = Fs[v];
+      sFs[k][q][v] = Fs[v];
+    }
+  }
+  __syncthreads();
+  if (tid < n) {
+    const int i = tid;
+    double* dst = const_cast<double*>(mv.mortar_flux) + (((size_t)b * mv.nrows + r.row_c) * n + i) * NV;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int q = 0; q < n; ++q) s = fma(mv.K->Pr[k][i * n + q], sFs[k][q][v], s);
+      dst[v] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+// ---------------------------------------------------------------------------
+template <int DIM, int N, class PHYS, typename T, bool MORTAR>
+static hipError_t go(const Ctx& c, const StageParams& sp, hipStream_t s) {
+  using SH = Shape<DIM, N>;
+  const int nEB = (c.E + SH::EPB - 1) / SH::EPB;
+  const int nblk = nEB * c.B;
+  hipLaunchKernelGGL((k_stage<DIM, N, PHYS, T, MORTAR>), dim3(nblk), dim3(SH::BS), 0, s, sp, mesh_view(c), c.pc);
+  return hipGetLastError();
+}
+
+template <int DIM, class PHYS, typename T, bool MORTAR>
+static hipError_t go_n(const Ctx& c, const StageParams& sp, hipStream_t s) {
+  switch (c.N) {
+    case 1: return go<DIM, 1, PHYS, T, MORTAR>(c, sp, s);
+    case 2: return go<DIM, 2, PHYS, T, MORTAR>(c, sp, s);
+    case 3: return go<DIM, 3, PHYS, T, MORTAR>(c, sp, s);
+    case 4: return go<DIM, 4, PHYS, T, MORTAR>(c, sp, s);
+    case 5: return go<DIM, 5, PHYS, T, MORTAR>(c, sp, s);
+    case 6: return go<DIM, 6, PHYS, T, MORTAR>(c, sp, s);
+    case 7: return go<DIM, 7, PHYS, T, MORTAR>(c, sp, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+static hipError_t stage_t(const Ctx& c, const StageParams& sp, hipStream_t s) {
+  if (c.desc.physics == DG_REACTING_EULER) {
+    if (c.dim == 2 && c.N == 3 && c.mech.nspecies == 5) return go<2, 3, ReactPhys<2, 5>, T, true>(c, sp, s);
+    return hipErrorInvalidValue;
+  }
+  if (c.dim == 2) return go_n<2, EulerPhys<2>, T, true>(c, sp, s);
+  return go_n<3, EulerPhys<3>, T, false>(c, sp, s);
+}
+
+hipError_t launch_stage(const Ctx& c, const StageParams& sp, hipStream_t s) {
+  return c.desc.precision == DG_F32 ? stage_t<float>(c, sp, s) : stage_t<double>(c, sp, s);
+}
+
+template <typename T>
+static hipError_t mortar_t(const Ctx& c, const void* U, hipStream_t s) {
+  const T* Ut = static_cast<const T*>(U);
+  dim3 grid(c.nmortar, c.B);
+  if (c.desc.physics == DG_REACTING_EULER) {
+    if (c.N == 3) {
+      hipLaunchKernelGGL((k_mortar<3, ReactPhys<2, 5>, T>), grid, dim3(64), 0, s, c.d_mortars, Ut, mesh_view(c), c.pc);
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
+  switch (c.N) {
+#define DG_MORTAR_CASE(NN)                                                                                      \
+  case NN:                                                                                                      \
+    hipLaunchKernelGGL((k_mortar<NN, EulerPhys<2>, T>), grid, dim3(64), 0, s, c.d_mortars, Ut, mesh_view(c), c.pc); \
+    return hipGetLastError();
+    DG_MORTAR_CASE(1)
+    DG_MORTAR_CASE(2)
+    DG_MORTAR_CASE(3)
+    DG_MORTAR_CASE(4)
+    DG_MORTAR_CASE(5)
+    DG_MORTAR_CASE(6)
+    DG_MORTAR_CASE(7)
+#undef DG_MORTAR_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_mortar(const Ctx& c, const void* U, hipStream_t s) {
+  if (c.nmortar == 0) return hipSuccess;
+  return c.desc.precision == DG_F32 ? mortar_t<float>(c, U, s) : mortar_t<double>(c, U, s);
+}
+
+}  // namespace dg

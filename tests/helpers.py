@@ -1,0 +1,67 @@
+"""Shared helpers of the GPU parity tests: build an oracle operator and a
+library context for the same problem, move states between them, and the
+norm-wise error used throughout (per variable, ||x - y||_inf / ||y||_inf)."""
+
+import numpy as np
+import torch
+
+import dginputs as di
+from oracle.dgsem import Operator
+from oracle.mesh import cartesian_mesh
+from oracle.physics import Euler, ReactingEuler
+
+
+def make_pair(dim, N, nel, lo, hi, physics="euler", precision="f64", batch=1, patch=None,
+              mu=0.0, prandtl=0.72, mech=None):
+    from paper_2605_26388_amd import Solver
+    plo, phi = patch if patch else (None, None)
+    mesh = cartesian_mesh(dim, N, nel, lo, hi, plo, phi)
+    viscous = None
+    if physics == "reacting":
+        phys = ReactingEuler(dim, mech)
+    else:
+        phys = Euler(dim)
+        if physics == "navier_stokes":
+            viscous = dict(mu=mu, prandtl=prandtl, gamma=1.4)
+    op = Operator(mesh, phys, viscous=viscous)
+    s = Solver(dim, N, nel, lo, hi, physics=physics, precision=precision, batch=batch,
+               patch_lo=plo, patch_hi=phi, mu=mu, prandtl=prandtl, mech=mech)
+    assert s.E == mesh.E
+    return op, s
+
+
+def to_gpu(s, U):
+    """Oracle layout (B, nv, E, n..n) float64 -> library tensor."""
+    return U.reshape(s.shape).to(device=s.device, dtype=s.dtype).contiguous()
+
+
+def from_gpu(op, X):
+    return X.detach().to("cpu", torch.float64).reshape((X.shape[0], X.shape[1], X.shape[2]) + (op.n,) * op.dim)
+
+
+def rel_err(got, ref):
+    """max over variables of ||got_v - ref_v||_inf / ||ref_v||_inf."""
+    B, nv = ref.shape[:2]
+    g = got.reshape(B, nv, -1).transpose(0, 1).reshape(nv, -1)
+    r = ref.reshape(B, nv, -1).transpose(0, 1).reshape(nv, -1)
+    num = (g - r).abs().amax(dim=1)
+    den = r.abs().amax(dim=1).clamp_min(1e-300)
+    return float((num / den).max())
+
+
+def random_euler_state(op, seed, B=1):
+    rng = np.random.default_rng(seed)
+    shape = (B, op.mesh.E) + (op.n,) * op.dim
+    rho = rng.uniform(0.5, 1.5, shape)
+    vel = [rng.uniform(-0.5, 0.5, shape) for _ in range(op.dim)]
+    p = rng.uniform(0.5, 1.5, shape)
+    return torch.tensor(np.stack([di.conserved_from_primitive(rho[b], [v[b] for v in vel], p[b], 1.4)
+                                  for b in range(B)]))
+
+
+def smooth_euler_state(op, B=1):
+    X = op.mesh.coords()
+    base = di.random_euler(X, op.mesh.lo, op.mesh.hi)
+    if B == 1:
+        return torch.tensor(base)[None]
+    return torch.tensor(np.stack([di.perturb_density(base, b) for b in range(B)]))

@@ -1,0 +1,175 @@
+"""GPU parity of the fused Euler stage (dg_rhs / dg_rk_stage) against the CPU
+FP64 oracle: element by element on small meshes (several workgroups and a
+ragged tail), every supported degree, batches, the 2:1 mortar mesh, the full
+32^3 workload, and the invariants (free stream, conservation, determinism,
+complete output coverage, non-physical state flagging, argument errors)."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import dginputs as di
+from oracle.timestep import rk_stage, ssprk33_step, integrals
+from helpers import make_pair, to_gpu, from_gpu, rel_err, random_euler_state, smooth_euler_state
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-12
+TWO_PI = 2 * math.pi
+
+
+@pytest.mark.parametrize("dim,N", [(2, 1), (2, 2), (2, 3), (2, 4), (2, 5), (2, 6), (2, 7),
+                                   (3, 1), (3, 2), (3, 3), (3, 4), (3, 5), (3, 6), (3, 7)])
+def test_rhs_parity_all_degrees(dim, N):
+    nel = (7, 5) if dim == 2 else (5, 3, 3)   # element counts leave a ragged last workgroup
+    lo = (0.0,) * dim
+    hi = (1.0, 1.3, 0.9)[:dim]
+    op, s = make_pair(dim, N, nel, lo, hi)
+    U = random_euler_state(op, 100 + N)
+    ref = op.rhs(U)
+    got = from_gpu(op, s.rhs(to_gpu(s, U)))
+    assert rel_err(got, ref) < TOL64
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_rk_stage_parity_batched(dim):
+    nel = (6, 9) if dim == 2 else (4, 5, 3)
+    lo, hi = (0.0,) * dim, (TWO_PI,) * dim
+    op, s = make_pair(dim, 3, nel, lo, hi, batch=3)
+    U0 = smooth_euler_state(op, B=3)
+    Uk = random_euler_state(op, 7, B=3)
+    for (a, b, c) in ((0.0, 1.0, 0.01), (0.75, 0.25, 0.0025), (1 / 3, 2 / 3, 0.02 / 3)):
+        ref = rk_stage(op, U0, Uk, a, b, c)
+        out = s.empty()
+        s.rk_stage(to_gpu(s, U0), to_gpu(s, Uk), out, a, b, c)
+        assert rel_err(from_gpu(op, out), ref) < TOL64
+
+
+def test_rk_stage_in_place_on_U0():
+    op, s = make_pair(3, 3, (3, 4, 3), (0, 0, 0), (1, 1, 1))
+    U0 = random_euler_state(op, 1)
+    Uk = random_euler_state(op, 2)
+    ref = rk_stage(op, U0, Uk, 1 / 3, 2 / 3, 0.01)
+    g0 = to_gpu(s, U0)
+    s.rk_stage(g0, to_gpu(s, Uk), g0, 1 / 3, 2 / 3, 0.01)
+    assert rel_err(from_gpu(op, g0), ref) < TOL64
+
+
+def test_mortar_mesh_parity_and_conservation():
+    op, s = make_pair(2, 3, (10, 8), (-5, -5), (5, 5), patch=((3, 2), (7, 5)))
+    U = torch.tensor(di.vortex(op.mesh.coords(), 0.0))[None]
+    U = U + 0.05 * random_euler_state(op, 3)  # rough on top of smooth
+    ref = op.rhs(U)
+    dU = s.rhs(to_gpu(s, U))
+    assert rel_err(from_gpu(op, dU), ref) < TOL64
+    I = s.integrals(dU)
+    scale = s.integrals(dU.abs())
+    assert np.abs(I[:, :-1] / scale[:, :-1]).max() < 1e-13
+
+
+def test_full_size_workload_parity():
+    """3-D Euler 32^3, N=3 smooth random state, the benchmark's launch shape."""
+    p = di.PRESETS["euler3d"]
+    op, s = make_pair(3, 3, p["nel"], p["lo"], p["hi"])
+    U = smooth_euler_state(op)
+    ref = op.rhs(U)
+    Ug = to_gpu(s, U)
+    got = from_gpu(op, s.rhs(Ug))
+    assert rel_err(got, ref) < TOL64
+    dt = s.dt_cfl(Ug, p["cfl"])
+    out = s.empty()
+    s.rk_stage(None, Ug, out, 0.0, 1.0, dt)
+    refs = rk_stage(op, U, U, 0.0, 1.0, dt)
+    assert rel_err(from_gpu(op, out), refs) < TOL64
+
+
+def test_large_workload_invariants():
+    """64^3: free stream is preserved and the RHS is conservative."""
+    p = di.PRESETS["euler3d_L"]
+    from paper_2605_26388_amd import Solver
+    s = Solver(3, 3, p["nel"], p["lo"], p["hi"])
+    U = s.empty()
+    U[:, 0] = 1.0
+    U[:, 1] = 0.3
+    U[:, 2] = -0.2
+    U[:, 3] = 0.1
+    U[:, 4] = 2.5 + 0.5 * (0.09 + 0.04 + 0.01)
+    dU = s.rhs(U)
+    assert float(dU.abs().max()) < 1e-13 * 3 * 9.1 * 2 / (TWO_PI / 64)
+    # conservation on a smooth state built from the library's own coordinates
+    X = s.node_coords().cpu().numpy()
+    Us = torch.tensor(di.random_euler(X, p["lo"], p["hi"]))[None].to(s.device).contiguous()
+    dU = s.rhs(Us)
+    I = s.integrals(dU)
+    scale = s.integrals(dU.abs())
+    assert np.abs(I[:, :-1] / np.maximum(scale[:, :-1], 1e-300)).max() < 1e-13
+    st = s.status()
+    assert st["nonphysical"] == 0
+
+
+def test_determinism_and_full_coverage():
+    op, s = make_pair(3, 4, (3, 5, 2), (0, 0, 0), (1, 2, 1))
+    U = random_euler_state(op, 5)
+    Ug = to_gpu(s, U)
+    a = torch.full(s.shape, float("nan"), dtype=s.dtype, device=s.device)
+    b = torch.full(s.shape, float("nan"), dtype=s.dtype, device=s.device)
+    s.rhs(Ug, a)
+    s.rhs(Ug, b)
+    assert not torch.isnan(a).any()
+    assert torch.equal(a, b)
+
+
+def test_nonphysical_flagged_and_reported():
+    op, s = make_pair(3, 2, (3, 3, 3), (0, 0, 0), (1, 1, 1))
+    U = random_euler_state(op, 9)
+    U[0, 0, 13, 1, 2, 0] = -0.5          # negative density at element 13
+    s.status(reset=True)
+    s.rhs(to_gpu(s, U))
+    st = s.status(reset=True)
+    assert st["nonphysical"] == 1
+    assert st["first_bad"] == 13 * 27 + (1 * 9 + 2 * 3 + 0)
+    assert s.status()["nonphysical"] == 0
+
+
+def test_argument_errors():
+    from paper_2605_26388_amd import DGError
+    op, s = make_pair(2, 3, (3, 3), (0, 0), (1, 1))
+    U = to_gpu(s, random_euler_state(op, 1))
+    with pytest.raises(DGError):
+        s.rk_stage(None, U, U, 0.0, 1.0, 0.1)     # Uout aliases Uk
+    with pytest.raises(DGError):
+        s.rhs(U, U)
+    with pytest.raises(ValueError):
+        s.rhs(U.float())
+
+
+def test_integrals_and_dt_match_oracle():
+    from oracle.timestep import dt_cfl
+    op, s = make_pair(2, 3, (8, 8), (-5, -5), (5, 5), batch=2)
+    U = torch.cat([torch.tensor(di.vortex(op.mesh.coords(), 0.0))[None],
+                   torch.tensor(di.vortex(op.mesh.coords(), 1.0))[None]])
+    Ug = to_gpu(s, U)
+    I = s.integrals(Ug)
+    Iref = integrals(op, U)
+    assert np.abs(I - Iref).max() <= 1e-13 * np.abs(Iref).max()
+    assert abs(s.dt_cfl(Ug, 0.5) / dt_cfl(op, U, 0.5) - 1) < 1e-14
+    X = s.node_coords().cpu().numpy().reshape((2, op.mesh.E) + (4, 4))
+    assert np.abs(X - op.mesh.coords()).max() < 1e-14
+
+
+def test_vortex_run_matches_oracle():
+    """The 2-D vortex workload (8^2, N=3): 20 SSP-RK3 steps at CFL 0.5."""
+    p = di.PRESETS["vortex2d"]
+    op, s = make_pair(2, 3, p["nel"], p["lo"], p["hi"])
+    U = torch.tensor(di.vortex(op.mesh.coords(), 0.0))[None]
+    Ug = to_gpu(s, U)
+    dt = s.dt_cfl(Ug, p["cfl"])
+    for _ in range(p["steps"]):
+        U = ssprk33_step(op, U, dt)
+        s.ssprk3_step(Ug, dt)
+    assert rel_err(from_gpu(op, Ug), U) < TOL64
+    # density error against the exact translated vortex is the discretisation's
+    ex = torch.tensor(di.vortex(op.mesh.coords(), p["steps"] * dt))[None]
+    got = from_gpu(op, Ug)
+    assert float((got[0, 0] - ex[0, 0]).abs().max()) < 5e-2   # 8^2 elements, h = 1.25
