@@ -440,8 +440,8 @@ int dg_create(const dg_desc* desc, dg_ctx** out) {
       break;
     case DG_REACTING_EULER:
       if (d.dim != 2 || d.degree != 3) return fail(DG_ERR_UNSUPPORTED, "reacting Euler: 2-D, degree 3");
-      if (!d.mech || d.mech->nspecies != 5 || d.mech->nreactions < 1 || d.mech->nreactions > DG_MAX_REACTIONS)
-        return fail(DG_ERR_UNSUPPORTED, "reacting Euler: mechanism with 5 species and 1..8 reactions");
+      if (!d.mech || d.mech->nspecies != 5 || d.mech->nreactions != 5)
+        return fail(DG_ERR_UNSUPPORTED, "reacting Euler: mechanism with 5 species and 5 reactions");
       break;
     default: return fail(DG_ERR_ARG, "unknown physics");
   }
