@@ -80,10 +80,7 @@ def time_adjoint(solver, U, dt, steps, warmup):
     mu2, mu1, acc, out = solver.empty(), solver.empty(), solver.empty(), solver.empty()
 
     def step():
-        acc.zero_()
-        solver.rk_stage_adjoint(Us[2], lam, mu2, acc, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0 * dt)
-        solver.rk_stage_adjoint(Us[1], mu2, mu1, acc, 0.75, 0.25, 0.25 * dt)
-        solver.rk_stage_adjoint(Us[0], mu1, out, acc, 0.0, 1.0, dt, accumulate=True)
+        solver.ssprk3_step_adjoint(Us, dt, lam, out, acc, mu2, mu1)
 
     for _ in range(warmup):
         step()

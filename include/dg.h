@@ -155,18 +155,23 @@ int dg_source_chem(dg_ctx* ctx, const void* U, void* out, double h, int32_t mode
 /* Discrete adjoint of L (Euler physics, conforming meshes):
  * lam_U = (dL/dU)^T lam_L evaluated at U, in gather form (no atomics).
  * Subgradient convention at kinks: d max(x,y) -> x when x >= y, d|x| -> +1
- * when x >= 0.  lam_U must not alias U or lam_L. */
+ * when x >= 0.  Supported degrees 1..4.  lam_U must not alias U or lam_L. */
 int dg_rhs_adjoint(dg_ctx* ctx, const void* U, const void* lam_L, void* lam_U, void* stream);
 
-/* Adjoint of the fused stage Uout = a U0 + b Uk + c_dt L(Uk) at Uk:
- *   lam_k = b lam_out + c_dt (dL/dU(Uk))^T lam_out + (accumulate ? lam_0 : 0)
- *   lam_0 = lam_0 + a lam_out                       (when lam_0 != NULL and
- *                                                    accumulate == 0)
- * With accumulate != 0 the accumulated lam_0 is folded into lam_k and lam_0
- * is left unchanged (used by the first stage of a step).  lam_k must not
- * alias Uk or lam_out; lam_0 may not alias lam_out. */
+/* Adjoint of the fused stage Uout = a U0 + b Uk + c_dt L(Uk) at Uk
+ * (Euler physics, conforming meshes; same conventions as dg_rhs_adjoint):
+ *   lam_k = b lam_out + c_dt (dL/dU(Uk))^T lam_out     (+ lam_0 for DG_LAM0_FOLD)
+ * and, depending on lam0_mode,
+ *   DG_LAM0_ACCUMULATE: lam_0 = lam_0 + a lam_out,
+ *   DG_LAM0_INIT:       lam_0 = a lam_out (lam_0 not read),
+ *   DG_LAM0_FOLD:       lam_0 is only read (folded into lam_k).
+ * lam_0 may be NULL (then it is neither read nor written).  This is what the
+ * reverse sweep of one Shu-Osher step needs: INIT for the last stage,
+ * ACCUMULATE for the middle one, FOLD for the first.  lam_k must not alias
+ * Uk, lam_out or lam_0; lam_0 must not alias lam_out or Uk. */
+enum { DG_LAM0_ACCUMULATE = 0, DG_LAM0_FOLD = 1, DG_LAM0_INIT = 2 };
 int dg_rk_stage_adjoint(dg_ctx* ctx, const void* Uk, const void* lam_out, void* lam_k,
-                        void* lam_0, double a, double b, double c_dt, int32_t accumulate,
+                        void* lam_0, double a, double b, double c_dt, int32_t lam0_mode,
                         void* stream);
 
 /* Largest stable time step from the CFL bounds (SSP-RK appendix):

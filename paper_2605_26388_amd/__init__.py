@@ -7,3 +7,4 @@ include/dg.h); this package is its thin binding.  Build it with
 
 from ._abi import DGError, load  # noqa: F401
 from .solver import Solver, mechanism_struct  # noqa: F401
+from .rollout import DGRollout  # noqa: F401

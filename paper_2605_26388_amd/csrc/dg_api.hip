@@ -522,8 +522,9 @@ int dg_create(const dg_desc* desc, dg_ctx** out) {
     }
   }
   if (d.physics == DG_NAVIER_STOKES) {
-    // BR1 face buffer: [B][E][2*dim][n^2][nv] in the context precision
-    const size_t bytes = (size_t)c.B * c.E * 2 * c.dim * c.n * c.n * c.nv * (d.precision == DG_F32 ? 4 : 8);
+    // BR1 face buffer: [B][E][2*dim][n^2][4] (momentum and energy rows of the
+    // normal viscous flux) in the context precision
+    const size_t bytes = (size_t)c.B * c.E * 2 * c.dim * c.n * c.n * 4 * (d.precision == DG_F32 ? 4 : 8);
     if ((e = upload(&c.d_face, nullptr, bytes)) != hipSuccess) {
       free_ctx(c);
       delete ctx;
@@ -617,8 +618,8 @@ int dg_source_chem(dg_ctx* ctx, const void* U, void* out, double h, int32_t mode
 int dg_rhs_adjoint(dg_ctx* ctx, const void* U, const void* lam_L, void* lam_U, void* stream) {
   if (!ctx || !U || !lam_L || !lam_U) return fail(DG_ERR_ARG, "dg_rhs_adjoint: null argument");
   Ctx& c = ctx->c;
-  if (c.desc.physics != DG_EULER || c.nmortar > 0)
-    return fail(DG_ERR_UNSUPPORTED, "adjoint: Euler physics on conforming meshes");
+  if (c.desc.physics != DG_EULER || c.nmortar > 0 || c.N > 4)
+    return fail(DG_ERR_UNSUPPORTED, "adjoint: Euler physics on conforming meshes, degree <= 4");
   const size_t bytes = state_bytes(c);
   if (overlaps(lam_U, U, bytes) || overlaps(lam_U, lam_L, bytes))
     return fail(DG_ERR_ARG, "dg_rhs_adjoint: lam_U aliases an input");
@@ -628,19 +629,20 @@ int dg_rhs_adjoint(dg_ctx* ctx, const void* U, const void* lam_L, void* lam_U, v
 }
 
 int dg_rk_stage_adjoint(dg_ctx* ctx, const void* Uk, const void* lam_out, void* lam_k, void* lam_0, double a,
-                        double b, double c_dt, int32_t accumulate, void* stream) {
+                        double b, double c_dt, int32_t lam0_mode, void* stream) {
   if (!ctx || !Uk || !lam_out || !lam_k) return fail(DG_ERR_ARG, "dg_rk_stage_adjoint: null argument");
   Ctx& c = ctx->c;
-  if (c.desc.physics != DG_EULER || c.nmortar > 0)
-    return fail(DG_ERR_UNSUPPORTED, "adjoint: Euler physics on conforming meshes");
-  if (accumulate && !lam_0) return fail(DG_ERR_ARG, "dg_rk_stage_adjoint: accumulate needs lam_0");
+  if (c.desc.physics != DG_EULER || c.nmortar > 0 || c.N > 4)
+    return fail(DG_ERR_UNSUPPORTED, "adjoint: Euler physics on conforming meshes, degree <= 4");
+  if (lam0_mode != DG_LAM0_ACCUMULATE && lam0_mode != DG_LAM0_FOLD && lam0_mode != DG_LAM0_INIT)
+    return fail(DG_ERR_ARG, "dg_rk_stage_adjoint: unknown lam0_mode");
   const size_t bytes = state_bytes(c);
-  if (overlaps(lam_k, Uk, bytes) || overlaps(lam_k, lam_out, bytes))
+  if (overlaps(lam_k, Uk, bytes) || overlaps(lam_k, lam_out, bytes) || overlaps(lam_k, lam_0, bytes))
     return fail(DG_ERR_ARG, "dg_rk_stage_adjoint: lam_k aliases an input");
-  if (lam_0 && (overlaps(lam_0, lam_out, bytes) || overlaps(lam_0, Uk, bytes) || overlaps(lam_0, lam_k, bytes)))
+  if (lam_0 && (overlaps(lam_0, lam_out, bytes) || overlaps(lam_0, Uk, bytes)))
     return fail(DG_ERR_ARG, "dg_rk_stage_adjoint: lam_0 aliases another buffer");
   DeviceGuard guard(c.device);
-  hipError_t e = launch_adjoint(c, Uk, lam_out, lam_k, lam_0, a, b, c_dt, accumulate, static_cast<hipStream_t>(stream));
+  hipError_t e = launch_adjoint(c, Uk, lam_out, lam_k, lam_0, a, b, c_dt, lam0_mode, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? DG_OK : hip_fail(e, "dg_rk_stage_adjoint");
 }
 

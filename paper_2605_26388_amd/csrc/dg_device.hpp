@@ -24,8 +24,9 @@ struct Shape {
   static constexpr int n = N + 1;
   static constexpr int NP = ipow(n, DIM);       // nodes per element
   static constexpr int NF = ipow(n, DIM - 1);   // nodes per face
-  // elements per workgroup: fill ~256 lanes, at least one element
-  static constexpr int EPB = NP >= 256 ? 1 : 256 / NP;
+  // elements per workgroup: one wave's worth of lanes, at least one element
+  // (small workgroups keep the barrier local to one element's wave)
+  static constexpr int EPB = NP >= 64 ? 1 : 64 / NP;
   static constexpr int NT = EPB * NP;
   static constexpr int BS = ((NT + 63) / 64) * 64;
 };
@@ -59,23 +60,29 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void* base, size_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)(unsigned)bytes, 0x00020000);
 }
 
+// Element index i within the descriptor's range; the optional soff is a
+// uniform byte offset (e.g. of a variable plane) added in a scalar register.
 template <typename T> struct Buf;
 template <> struct Buf<double> {
-  static __device__ __forceinline__ double load(rsrc_t r, unsigned i) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, i * 8u, 0, 0));
+  static __device__ __forceinline__ double load(rsrc_t r, unsigned i, unsigned soff = 0) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, i * 8u, soff, 0));
   }
-  static __device__ __forceinline__ void store(rsrc_t r, unsigned i, double x) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, i * 8u, 0, 0);
+  static __device__ __forceinline__ void store(rsrc_t r, unsigned i, double x, unsigned soff = 0) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, i * 8u, soff, 0);
   }
 };
 template <> struct Buf<float> {
-  static __device__ __forceinline__ double load(rsrc_t r, unsigned i) {
-    return static_cast<double>(__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, i * 4u, 0, 0)));
+  static __device__ __forceinline__ double load(rsrc_t r, unsigned i, unsigned soff = 0) {
+    return static_cast<double>(__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, i * 4u, soff, 0)));
   }
-  static __device__ __forceinline__ void store(rsrc_t r, unsigned i, double x) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, static_cast<float>(x)), r, i * 4u, 0, 0);
+  static __device__ __forceinline__ void store(rsrc_t r, unsigned i, double x, unsigned soff = 0) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, static_cast<float>(x)), r, i * 4u, soff, 0);
   }
 };
+
+// Make a value the compiler cannot prove uniform a scalar (only valid when it
+// is uniform across the wave).
+__device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // Reciprocal and square root for the hot loops: hardware estimate refined by
 // Newton-Raphson (reciprocal) and the coupled Goldschmidt iteration (square

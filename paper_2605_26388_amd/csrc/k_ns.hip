@@ -1,0 +1,311 @@
+// Compressible Navier-Stokes stage with BR1 viscous terms (Kernel
+// Architecture for Parabolic Terms: eqs. br1_avg, tau, br1_flux; the BR1
+// paragraphs of the strong-form appendix), 3-D affine Cartesian elements.
+//
+// Two passes per evaluation of L, each finishing before the next:
+//   pass 1 (k_br1_face): per element, the lifted gradient S = grad W of the
+//     primitive variables W = (rho, u, v, w, T) (only u, v, w, T enter the
+//     viscous flux), with the central trace W^ = (W^- + W^+)/2 on every face;
+//     then the viscous flux normal to each face, F_v^l(U, S), at the element's
+//     own face nodes is written to a face buffer [B][E][2*DIM][n^2][4]
+//     (momentum and energy components; the mass component is zero).
+//   pass 2 (k_ns_stage): recomputes S at all nodes (again with the neighbour
+//     traces), forms the combined flux G^l = F_inv^l - F_v^l, takes its
+//     strong-form divergence with the LGL derivative matrix, adds the surface
+//     lift of the Rusanov inviscid flux and of the central viscous flux
+//     {{F_v}} = (F_v^- + F_v^+)/2 built from the face buffer (both sides read
+//     the same two buffer values, so the interface flux is single-valued), and
+//     applies the Shu-Osher stage update.
+// Closure: non-dimensional R = 1 so T = p / rho; Newtonian stress with the
+// Stokes hypothesis; q = -k grad T with k = gamma mu / (Pr (gamma - 1)).
+// LDS operands stay in double for both state precisions.
+#include <type_traits>
+
+#include "dg_device.hpp"
+
+namespace dg {
+
+constexpr int NS_DIM = 3;
+
+// face-node index of node (i, j, k) on a face normal to direction l
+template <int n>
+__device__ __forceinline__ int face_node(const int (&ii)[3], int l) {
+  return l == 0 ? ii[1] + n * ii[2] : (l == 1 ? ii[0] + n * ii[2] : ii[0] + n * ii[1]);
+}
+
+// W = (u, v, w, T) from the conserved state (rho is not needed by F_v)
+__device__ __forceinline__ void prim_w(const double (&U)[5], double gm1, double (&W)[4]) {
+  const double ri = frcp(U[0]);
+  double m2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    W[d] = U[1 + d] * ri;
+    m2 = fma(U[1 + d], U[1 + d], m2);
+  }
+  const double p = gm1 * fma(-0.5 * m2, ri, U[4]);
+  W[3] = p * ri;
+}
+
+// Viscous flux along direction l (momentum and energy rows) from the
+// velocity, the gradient S[d][q] = d W_q / d x_d and mu, k.
+__device__ __forceinline__ void visc_flux(const double (&W)[4], const double (&S)[3][4], int l, double mu, double kc,
+                                          double (&Fv)[4]) {
+  const double div = S[0][0] + S[1][1] + S[2][2];
+  double e = kc * S[l][3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double t = mu * (S[d][l] + S[l][d]);
+    if (d == l) t = fma(-2.0 / 3.0 * mu, div, t);
+    Fv[d] = t;
+    e = fma(W[d], t, e);
+  }
+  Fv[3] = e;
+}
+
+template <int N, typename T, int PASS>
+__global__ void __launch_bounds__((Shape<3, N>::BS))
+k_ns(StageParams sp, MeshView mv, PhysConst pc, T* face) {
+  using S = Shape<3, N>;
+  constexpr int n = S::n, NP = S::NP, NF = S::NF, EPB = S::EPB, NV = 5;
+  using PHYS = EulerPhys<3>;
+
+  __shared__ double sW[4][EPB * NP];
+  __shared__ double sF[PASS == 2 ? 3 : 1][NV][PASS == 2 ? EPB * NP : 1];
+  __shared__ double sD[n * n];
+
+  const int tid = threadIdx.x;
+  for (int q = tid; q < n * n; q += S::BS) sD[q] = mv.K->D[q];
+
+  const int E = mv.E;
+  const int nEB = (E + EPB - 1) / EPB;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = blk / nEB;
+  const int eb = blk - b * nEB;
+  const int el = tid / NP;
+  const int node = tid - el * NP;
+  const int e = eb * EPB + el;
+  const bool active = (tid < S::NT) && (e < E);
+  const int ec = active ? e : 0;
+  int ii[3];
+  ii[0] = node % n;
+  ii[1] = (node / n) % n;
+  ii[2] = node / (n * n);
+  const int stride[3] = {1, n, n * n};
+
+  const size_t plane = (size_t)E * NP;
+  const size_t pbytes = plane * sizeof(T);
+  const T* Ub = static_cast<const T*>(sp.Uk) + (size_t)b * NV * plane;
+  rsrc_t rU[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) rU[v] = make_rsrc(Ub + v * plane, pbytes);
+  const unsigned off = (unsigned)(ec * NP + node);
+  double u[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u[v] = Buf<T>::load(rU[v], off);
+
+  int side[3], nbe[3];
+  double un[3][NV];
+  const int* nb = mv.nbr + (size_t)ec * 6;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    side[l] = (ii[l] == 0) ? 0 : ((ii[l] == N) ? 1 : -1);
+    nbe[l] = (active && side[l] >= 0) ? nb[2 * l + side[l]] : -1;
+    if (nbe[l] >= 0) {
+      const unsigned noff = (unsigned)(nbe[l] * NP + node + (side[l] ? -N : N) * stride[l]);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) un[l][v] = Buf<T>::load(rU[v], noff);
+    }
+  }
+  const bool use_u0 = (PASS == 2) && (sp.mode != 0) && (sp.a != 0.0);
+  double u0[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u0[v] = 0.0;
+  if (use_u0 && active) {
+    const T* U0b = static_cast<const T*>(sp.U0) + (size_t)b * NV * plane;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u0[v] = Buf<T>::load(make_rsrc(U0b + v * plane, pbytes), off);
+  }
+
+  const double gm1 = pc.gamma - 1.0;
+  const double mu = pc.mu;
+  const double kc = pc.gamma * pc.mu / (pc.prandtl * gm1);
+  double W[4];
+  prim_w(u, gm1, W);
+  if (tid < S::NT) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sW[q][tid] = W[q];
+  }
+  __syncthreads();
+
+  double g[3];
+#pragma unroll
+  for (int l = 0; l < 3; ++l) g[l] = mv.geo[(size_t)ec * 4 + l];
+  const double winv = mv.K->wend_inv;
+
+  // ---- lifted gradient S[l][q] = dW_q / dx_l --------------------------------
+  double Sg[3][4];
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Sg[l][q] = 0.0;
+  if (tid < S::NT) {
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      const int il = ii[l], st = stride[l];
+      const int base = tid - il * st;
+      double dr[n];
+#pragma unroll
+      for (int m = 0; m < n; ++m) dr[m] = sD[il * n + m];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m < n; ++m) s = fma(dr[m], sW[q][base + m * st], s);
+        Sg[l][q] = s;
+      }
+      if (nbe[l] >= 0) {
+        // W^ - W_own = (W_nbr - W_own)/2; + on the upper face, - on the lower
+        double Wn[4];
+        prim_w(un[l], gm1, Wn);
+        const double c = (side[l] ? 0.5 : -0.5) * winv;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Sg[l][q] = fma(c, Wn[q] - W[q], Sg[l][q]);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Sg[l][q] *= g[l];
+    }
+  }
+
+  if constexpr (PASS == 1) {
+    // normal viscous flux at the element's own face nodes -> face buffer
+    if (active) {
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        if (side[l] < 0) continue;
+        double Fv[4];
+        visc_flux(W, Sg, l, mu, kc, Fv);
+        const int f = 2 * l + side[l];
+        T* dst = face + ((((size_t)b * E + e) * 6 + f) * NF + face_node<n>(ii, l)) * 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dst[q] = static_cast<T>(Fv[q]);
+      }
+    }
+    return;
+  } else {
+    // ---- combined flux G^l = F_inv^l - F_v^l in LDS -------------------------
+    Thermo th;
+    const bool ok = PHYS::thermo(u, th, pc);
+    if (active && !ok)
+      report_nonphysical(mv.counters, mv.first_bad, ((unsigned long long)b * E + e) * NP + node);
+    double vel[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) vel[d] = u[1 + d] * th.ri;
+    if (tid < S::NT) {
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        double F[NV], Fv[4];
+        PHYS::flux(u, vel[l], th.p, l, F);
+        visc_flux(W, Sg, l, mu, kc, Fv);
+        sF[l][0][tid] = F[0];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sF[l][1 + q][tid] = F[1 + q] - Fv[q];
+      }
+    }
+    __syncthreads();
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    if (tid < S::NT) {
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        const int il = ii[l], st = stride[l];
+        const int base = tid - il * st;
+        double dr[n];
+#pragma unroll
+        for (int m = 0; m < n; ++m) dr[m] = sD[il * n + m] * (-g[l]);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          double s = 0.0;
+#pragma unroll
+          for (int m = 0; m < n; ++m) s = fma(dr[m], sF[l][v][base + m * st], s);
+          acc[v] += s;
+        }
+      }
+    }
+    // ---- surface terms ----------------------------------------------------------
+    bool on_face = side[0] >= 0 || side[1] >= 0 || side[2] >= 0;
+    if (active && on_face) {
+      const double aown = sound<PHYS>(th);
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        if (side[l] < 0) continue;
+        double Fo[NV], Fn[NV], Fs[NV];
+        PHYS::flux(u, vel[l], th.p, l, Fo);
+        Thermo tn;
+        PHYS::thermo(un[l], tn, pc);
+        const double vn = un[l][1 + l] * tn.ri;
+        PHYS::flux(un[l], vn, tn.p, l, Fn);
+        const double co = fabs(vel[l]) + aown;
+        const double cn = fabs(vn) + sound<PHYS>(tn);
+        const double hl = 0.5 * (co >= cn ? co : cn);
+        const double hs = side[l] ? hl : -hl;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Fs[v] = fma(-hs, un[l][v] - u[v], 0.5 * (Fo[v] + Fn[v]));
+        // central viscous flux from the two buffered face values
+        const int q = face_node<n>(ii, l);
+        const T* own = face + ((((size_t)b * E + e) * 6 + 2 * l + side[l]) * NF + q) * 4;
+        const T* oth = face + ((((size_t)b * E + nbe[l]) * 6 + 2 * l + 1 - side[l]) * NF + q) * 4;
+        const double sc = (side[l] ? -g[l] : g[l]) * winv;
+        acc[0] = fma(sc, Fs[0] - Fo[0], acc[0]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double fo = static_cast<double>(own[c]);
+          const double fv = 0.5 * (fo + static_cast<double>(oth[c]));
+          // combined jump: (F* - F) - (Fv* - Fv)
+          acc[1 + c] = fma(sc, (Fs[1 + c] - Fo[1 + c]) - (fv - fo), acc[1 + c]);
+        }
+      }
+    }
+    if (active) {
+      T* outb = static_cast<T*>(sp.out) + (size_t)b * NV * plane;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double r = acc[v];
+        if (sp.mode != 0) {
+          r = fma(sp.c, acc[v], sp.b * u[v]);
+          if (use_u0) r = fma(sp.a, u0[v], r);
+        }
+        Buf<T>::store(make_rsrc(outb + v * plane, pbytes), off, r);
+      }
+    }
+  }
+}
+
+template <int N, typename T>
+static hipError_t ns_go(const Ctx& c, const StageParams& sp, hipStream_t s) {
+  using SH = Shape<3, N>;
+  const int nEB = (c.E + SH::EPB - 1) / SH::EPB;
+  const int nblk = nEB * c.B;
+  T* face = static_cast<T*>(c.d_face);
+  hipLaunchKernelGGL((k_ns<N, T, 1>), dim3(nblk), dim3(SH::BS), 0, s, sp, mesh_view(c), c.pc, face);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_ns<N, T, 2>), dim3(nblk), dim3(SH::BS), 0, s, sp, mesh_view(c), c.pc, face);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t ns_t(const Ctx& c, const StageParams& sp, hipStream_t s) {
+  switch (c.N) {
+    case 2: return ns_go<2, T>(c, sp, s);
+    case 3: return ns_go<3, T>(c, sp, s);
+    case 4: return ns_go<4, T>(c, sp, s);
+  }
+  return hipErrorNotSupported;
+}
+
+hipError_t launch_ns(const Ctx& c, const StageParams& sp, hipStream_t s) {
+  return c.desc.precision == DG_F32 ? ns_t<float>(c, sp, s) : ns_t<double>(c, sp, s);
+}
+
+}  // namespace dg

@@ -32,11 +32,13 @@ template <> __device__ __forceinline__ double dmat_entry<double>(const RefConsts
 template <> __device__ __forceinline__ float dmat_entry<float>(const RefConsts* K, int q) { return K->Df[q]; }
 
 template <int DIM, int N, class PHYS, typename T, bool MORTAR>
-__global__ void __launch_bounds__((Shape<DIM, N>::BS))
+__global__ void __launch_bounds__((Shape<DIM, N>::BS)) __attribute__((amdgpu_waves_per_eu(4)))
 k_stage(StageParams sp, MeshView mv, PhysConst pc) {
   using S = Shape<DIM, N>;
   constexpr int n = S::n, NP = S::NP, EPB = S::EPB, NV = PHYS::NV, MOM = PHYS::MOM;
   constexpr bool F32 = std::is_same<T, float>::value;
+  // an element fills whole waves: its index and tables are wave-uniform
+  constexpr bool UNIFORM_ELEM = (NP % 64) == 0;
 
   __shared__ T sF[DIM][NV][EPB * NP];
   __shared__ T sD[n * n];
@@ -52,9 +54,10 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
   const int eb = blk - b * nEB;
   const int el = tid / NP;
   const int node = tid - el * NP;
-  const int e = eb * EPB + el;
+  int e = eb * EPB + el;
   const bool active = (tid < S::NT) && (e < E);
-  const int ec = active ? e : 0;  // clamped for address arithmetic only
+  int ec = active ? e : 0;  // clamped for address arithmetic only
+  if constexpr (UNIFORM_ELEM) ec = wave_uniform(ec);
 
   int ii[3];
   ii[0] = node % n;
@@ -62,41 +65,44 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
   ii[2] = node / (n * n);
   const int stride[3] = {1, n, n * n};
 
-  // One buffer descriptor per variable plane (scalar registers); per-lane
-  // element offsets are 32-bit.
+  // One buffer descriptor per state array (this batch member); variable
+  // planes are reached through a scalar byte offset.
   const size_t plane = (size_t)E * NP;
-  const size_t pbytes = plane * sizeof(T);
-  const T* Ub = static_cast<const T*>(sp.Uk) + (size_t)b * NV * plane;
-  rsrc_t rU[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) rU[v] = make_rsrc(Ub + v * plane, pbytes);
+  const size_t abytes = (size_t)NV * plane * sizeof(T);
+  const unsigned pstride = (unsigned)(plane * sizeof(T));
+  const rsrc_t rU = make_rsrc(static_cast<const T*>(sp.Uk) + (size_t)b * NV * plane, abytes);
   const unsigned off = (unsigned)(ec * NP + node);
 
   double u[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) u[v] = Buf<T>::load(rU[v], off);
+  for (int v = 0; v < NV; ++v) u[v] = Buf<T>::load(rU, off, v * pstride);
 
-  // Face lanes prefetch the neighbour's matching node for every face they lie on.
+  // Neighbour's matching node for each direction.  A lane that is not on a
+  // face in direction l uses its own node: the interface flux of a state
+  // with itself is its physical flux, so that direction's correction below
+  // is exactly zero and no lane has to branch.
   int side[DIM], nbe[DIM];
   double un[DIM][NV];
   const int* nb = mv.nbr + (size_t)ec * 2 * DIM;
 #pragma unroll
   for (int l = 0; l < DIM; ++l) {
     side[l] = (ii[l] == 0) ? 0 : ((ii[l] == N) ? 1 : -1);
-    nbe[l] = (active && side[l] >= 0) ? nb[2 * l + side[l]] : -1;
-    if (nbe[l] >= 0) {
-      const unsigned noff = (unsigned)(nbe[l] * NP + node + (side[l] ? -N : N) * stride[l]);
+    const int lo = nb[2 * l], hi = nb[2 * l + 1];
+    nbe[l] = side[l] == 0 ? lo : (side[l] == 1 ? hi : ec);
+    const bool conf = !MORTAR || nbe[l] >= 0;
+    const int ne = conf ? nbe[l] : ec;
+    const int shift = side[l] == 1 ? -N : (side[l] == 0 ? N : 0);
+    const unsigned noff = (unsigned)(ne * NP + node + shift * stride[l]);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) un[l][v] = Buf<T>::load(rU[v], noff);
-    }
+    for (int v = 0; v < NV; ++v) un[l][v] = Buf<T>::load(rU, noff, v * pstride);
   }
   // stage input U0, fetched early as well
   const bool use_u0 = (sp.mode != 0) && (sp.a != 0.0);
   double u0[NV];
-  if (use_u0 && active) {
-    const T* U0b = static_cast<const T*>(sp.U0) + (size_t)b * NV * plane;
+  if (use_u0) {
+    const rsrc_t r0 = make_rsrc(static_cast<const T*>(sp.U0) + (size_t)b * NV * plane, abytes);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) u0[v] = Buf<T>::load(make_rsrc(U0b + v * plane, pbytes), off);
+    for (int v = 0; v < NV; ++v) u0[v] = Buf<T>::load(r0, off, v * pstride);
   } else {
 #pragma unroll
     for (int v = 0; v < NV; ++v) u0[v] = 0.0;
@@ -165,58 +171,53 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
   }
 
   // ---- surface lift (eq. surf_int) ----------------------------------------
-  bool on_face = false;
+  const double aown = sound<PHYS>(th);
+  const double winv = mv.K->wend_inv;
 #pragma unroll
-  for (int l = 0; l < DIM; ++l) on_face |= side[l] >= 0;
-  if (active && on_face) {
-    const double aown = sound<PHYS>(th);
-    const double winv = mv.K->wend_inv;
+  for (int l = 0; l < DIM; ++l) {
+    double Fo[NV], Fs[NV];
+    PHYS::flux(u, vel[l], th.p, l, Fo);
+    // Rusanov flux with the element on the -xi_l side as left state, written
+    // in own/neighbour form: the average is symmetric and the jump term
+    // changes sign with the side, both exactly, so the two elements of a
+    // face obtain the same bits.
+    Thermo tn;
+    PHYS::thermo(un[l], tn, pc);
+    const double vn = un[l][MOM + l] * tn.ri;
+    double Fn[NV];
+    PHYS::flux(un[l], vn, tn.p, l, Fn);
+    const double co = fabs(vel[l]) + aown;
+    const double cn = fabs(vn) + sound<PHYS>(tn);
+    const double hl = 0.5 * (co >= cn ? co : cn);
+    const double hs = side[l] == 1 ? hl : -hl;
 #pragma unroll
-    for (int l = 0; l < DIM; ++l) {
-      if (side[l] < 0) continue;
-      double Fo[NV], Fs[NV];
-      PHYS::flux(u, vel[l], th.p, l, Fo);
-      if (!MORTAR || nbe[l] >= 0) {
-        // Rusanov flux with the element on the -xi_l side as left state.
-        // Written in own/neighbour form: the average is symmetric and the
-        // jump term changes sign with the side, both exactly, so the two
-        // elements of a face obtain the same bits.
-        Thermo tn;
-        PHYS::thermo(un[l], tn, pc);
-        const double vn = un[l][MOM + l] * tn.ri;
-        double Fn[NV];
-        PHYS::flux(un[l], vn, tn.p, l, Fn);
-        const double co = fabs(vel[l]) + aown;
-        const double cn = fabs(vn) + sound<PHYS>(tn);
-        const double hl = 0.5 * (co >= cn ? co : cn);
-        const double hs = side[l] ? hl : -hl;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) Fs[v] = fma(-hs, un[l][v] - u[v], 0.5 * (Fo[v] + Fn[v]));
-      } else {
+    for (int v = 0; v < NV; ++v) Fs[v] = fma(-hs, un[l][v] - u[v], 0.5 * (Fo[v] + Fn[v]));
+    if constexpr (MORTAR) {
+      if (side[l] >= 0 && nbe[l] < 0) {  // 2:1 face: flux from the mortar kernel
         const int row = -nbe[l] - 1;
         const int t = (DIM == 2) ? ii[1 - l] : 0;
         const double* src = mv.mortar_flux + (((size_t)b * mv.nrows + row) * S::NF + t) * NV;
 #pragma unroll
         for (int v = 0; v < NV; ++v) Fs[v] = src[v];
       }
-      const double sc = (side[l] ? -g[l] : g[l]) * winv;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) acc[v] = fma(sc, Fs[v] - Fo[v], acc[v]);
     }
+    const double sc = (side[l] == 1 ? -g[l] : g[l]) * winv;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = fma(sc, Fs[v] - Fo[v], acc[v]);
   }
 
   // ---- output ----------------------------------------------------------------
   if (active) {
-    T* outb = static_cast<T*>(sp.out) + (size_t)b * NV * plane;
+    const rsrc_t ro = make_rsrc(static_cast<T*>(sp.out) + (size_t)b * NV * plane, abytes);
     if (sp.mode == 0) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Buf<T>::store(make_rsrc(outb + v * plane, pbytes), off, acc[v]);
+      for (int v = 0; v < NV; ++v) Buf<T>::store(ro, off, acc[v], v * pstride);
     } else {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         double r = fma(sp.c, acc[v], sp.b * u[v]);
         if (use_u0) r = fma(sp.a, u0[v], r);
-        Buf<T>::store(make_rsrc(outb + v * plane, pbytes), off, r);
+        Buf<T>::store(ro, off, r, v * pstride);
       }
     }
   }

@@ -131,12 +131,24 @@ class Solver:
                                       self._ptr(out, "lam_U"), _stream(self.device)), "dg_rhs_adjoint")
         return out
 
-    def rk_stage_adjoint(self, Uk, lam_out, lam_k, lam_0, a, b, c_dt, accumulate=False):
+    LAM0_ACCUMULATE, LAM0_FOLD, LAM0_INIT = 0, 1, 2
+
+    def rk_stage_adjoint(self, Uk, lam_out, lam_k, lam_0, a, b, c_dt, lam0_mode=0):
         check(self.lib.dg_rk_stage_adjoint(self._ctx, self._ptr(Uk, "Uk"), self._ptr(lam_out, "lam_out"),
                                            self._ptr(lam_k, "lam_k"), self._ptr(lam_0, "lam_0"), float(a),
-                                           float(b), float(c_dt), int(bool(accumulate)), _stream(self.device)),
+                                           float(b), float(c_dt), int(lam0_mode), _stream(self.device)),
               "dg_rk_stage_adjoint")
         return lam_k
+
+    def ssprk3_step_adjoint(self, states, dt, lam, lam_prev, acc, mu2, mu1):
+        """Reverse sweep of one SSP-RK3 step with stored stage states
+        (U^n, U1, U2): lam_prev = (dU^{n+1}/dU^n)^T lam.  Three library calls;
+        acc, mu2 and mu1 are scratch states."""
+        Un, U1, U2 = states
+        self.rk_stage_adjoint(U2, lam, mu2, acc, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0 * dt, self.LAM0_INIT)
+        self.rk_stage_adjoint(U1, mu2, mu1, acc, 0.75, 0.25, 0.25 * dt, self.LAM0_ACCUMULATE)
+        self.rk_stage_adjoint(Un, mu1, lam_prev, acc, 0.0, 1.0, dt, self.LAM0_FOLD)
+        return lam_prev
 
     def dt_cfl(self, U, cfl):
         dt = ctypes.c_double()
@@ -158,7 +170,8 @@ class Solver:
 
     # -- composite drivers (sequences of library calls) ------------------------
     def ssprk3_step(self, U, dt, tmp1=None, tmp2=None):
-        """One Shu-Osher SSP-RK3 step, in place on U (two scratch states)."""
+        """One Shu-Osher SSP-RK3 step, in place on U (two scratch states, which
+        hold the stage states U1 and U2 afterwards)."""
         t1 = self.empty() if tmp1 is None else tmp1
         t2 = self.empty() if tmp2 is None else tmp2
         self.rk_stage(None, U, t1, 0.0, 1.0, dt)

@@ -65,3 +65,28 @@ def smooth_euler_state(op, B=1):
     if B == 1:
         return torch.tensor(base)[None]
     return torch.tensor(np.stack([di.perturb_density(base, b) for b in range(B)]))
+
+
+def flux_scale(op, U):
+    """Per-variable size of the terms a right-hand side is assembled from:
+    (2/h_min) ||D||_inf max_l ||F_l,v||_inf.  Rounding in a sweep of D is
+    relative to this, not to the (possibly much smaller) result; e.g. at low
+    Mach number the momentum flux carries the large mean pressure."""
+    P = op.phys.prims(U)
+    Dn = float(op.D.abs().sum(1).max())
+    s = None
+    for l in range(op.dim):
+        F = op.phys.flux(U, l, P).abs()
+        m = F.transpose(0, 1).reshape(F.shape[1], -1).amax(dim=1)
+        s = m if s is None else torch.maximum(s, m)
+    return s * Dn * 2.0 / op.mesh.hmin()
+
+
+def rel_err_floor(got, ref, floor):
+    """max over variables of ||got_v - ref_v||_inf / max(||ref_v||_inf, floor_v)."""
+    B, nv = ref.shape[:2]
+    g = got.reshape(B, nv, -1).transpose(0, 1).reshape(nv, -1)
+    r = ref.reshape(B, nv, -1).transpose(0, 1).reshape(nv, -1)
+    num = (g - r).abs().amax(dim=1)
+    den = torch.maximum(r.abs().amax(dim=1), floor.to(r.dtype))
+    return float((num / den).max())

@@ -1,0 +1,69 @@
+"""GPU parity of the Navier-Stokes (BR1) stage against the CPU FP64 oracle:
+small meshes at N = 2, 3, 4 (ragged last workgroup), the full Taylor-Green
+workload (16^3, N = 4), conservation, and the TGV viscous-dissipation identity
+evaluated from the library's own right-hand sides."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import dginputs as di
+from oracle.timestep import rk_stage, tensor_weights
+from helpers import make_pair, to_gpu, from_gpu, rel_err, rel_err_floor, flux_scale, random_euler_state
+
+pytestmark = pytest.mark.gpu
+TWO_PI = 2 * math.pi
+P = di.PRESETS["tgv3d"]
+
+
+@pytest.mark.parametrize("N", [2, 3, 4])
+def test_ns_rhs_parity_small(N):
+    op, s = make_pair(3, N, (3, 4, 3), (0, 0, 0), (1.0, 1.2, 0.9), physics="navier_stokes",
+                      mu=2e-2, prandtl=0.72)
+    U = random_euler_state(op, 40 + N)
+    ref = op.rhs(U)
+    got = from_gpu(op, s.rhs(to_gpu(s, U)))
+    assert rel_err(got, ref) < 1e-12
+
+
+def test_ns_stage_parity_full_workload():
+    op, s = make_pair(3, P["N"], P["nel"], P["lo"], P["hi"], physics="navier_stokes",
+                      mu=P["mu"], prandtl=P["prandtl"])
+    U = torch.tensor(di.taylor_green(op.mesh.coords(), mach=P["mach"]))[None]
+    Ug = to_gpu(s, U)
+    dt = s.dt_cfl(Ug, P["cfl"])
+    # At Mach 0.1 the momentum flux carries the mean pressure 1/(gamma M^2),
+    # 700 times the pressure variation: rounding in the derivative sweeps
+    # (oracle and library alike) is relative to that, so the per-variable
+    # norm is floored at 1e-4 of the flux scale (about 1e-16 of the terms).
+    floor = 1e-4 * flux_scale(op, U)
+    dU = s.rhs(Ug)
+    assert rel_err_floor(from_gpu(op, dU), op.rhs(U), floor) < 1e-12
+    out = s.empty()
+    s.rk_stage(None, Ug, out, 0.0, 1.0, dt)
+    ref = rk_stage(op, U, U, 0.0, 1.0, dt)
+    assert rel_err_floor(from_gpu(op, out), ref, dt * floor) < 1e-12
+    I = s.integrals(dU)[:, :-1]
+    scale = s.integrals(dU.abs())[:, :-1]
+    assert np.abs(I / np.maximum(scale, 1e-300)).max() < 1e-13
+
+
+def test_tgv_viscous_dissipation_on_gpu():
+    """dE_k/dt of the viscous part at t = 0 equals -3/4 mu (rho = 1)."""
+    from paper_2605_26388_amd import Solver
+    nel = (8, 8, 8)
+    ns = Solver(3, 4, nel, P["lo"], P["hi"], physics="navier_stokes", mu=P["mu"], prandtl=P["prandtl"])
+    eu = Solver(3, 4, nel, P["lo"], P["hi"], physics="euler")
+    X = ns.node_coords().cpu().numpy()
+    U = torch.tensor(di.taylor_green(X, mach=P["mach"]))[None].to(ns.device).contiguous()
+    dv = ns.rhs(U) - eu.rhs(U)          # viscous part of L(U)
+    vel = U[:, 1:4] / U[:, 0:1]
+    rate = (vel * dv[:, 1:4]).sum(1, keepdim=True)                     # u . d(m)/dt
+    zero = torch.zeros_like(rate)
+    tmp = torch.cat([rate, zero, zero, zero, torch.ones_like(rate)], 1).contiguous()
+    # integrate u . dm/dt with the library's quadrature (first column)
+    val = eu.integrals(tmp)[0, 0] / TWO_PI ** 3
+    assert abs(val / (-0.75 * P["mu"]) - 1.0) < 1e-2
+    assert float(dv[:, 0].abs().max()) < 1e-12
