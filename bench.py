@@ -97,9 +97,10 @@ def time_adjoint(solver, U, dt, steps, warmup):
     return wall / steps, a.elapsed_time(b) * 1e-3 / steps
 
 
-def cpu_baseline(p, budget_s=20.0):
+def cpu_baseline(p, budget_s=15.0):
     """The CPU oracle (torch-CPU float64) timed on the host's cores on a
-    bounded sample: full RK stages on the full-size mesh until ~budget_s."""
+    bounded sample: full RK stages on the full-size mesh until ~budget_s, then
+    one stage on a single thread."""
     from oracle.dgsem import Operator
     from oracle.mesh import cartesian_mesh
     from oracle.physics import Euler
@@ -119,13 +120,126 @@ def cpu_baseline(p, budget_s=20.0):
         a, b, c = coefs[nstage % 3]
         Uk = rk_stage(op, U, Uk, a, b, c * dt)
         nstage += 1
-        if time.perf_counter() - t0 > budget_s or nstage >= 6:
+        if time.perf_counter() - t0 > budget_s or nstage >= 60:
             break
     el = time.perf_counter() - t0
     dof = mesh.E * mesh.Np * 5
-    return dict(value=dof * nstage / el, unit="DOF-updates/s per RK stage", cores=torch.get_num_threads(),
-                kind="oracle", sample=f"{nstage} full RK stages of the 32^3 N=3 mesh ({dof} DOF), "
-                f"{el:.1f} s, torch-CPU float64, {platform.processor() or platform.machine()}")
+    threads = torch.get_num_threads()
+    torch.set_num_threads(1)
+    t1 = time.perf_counter()
+    rk_stage(op, U, U, 0.0, 1.0, dt)
+    single = dof / (time.perf_counter() - t1)
+    torch.set_num_threads(threads)
+    return dict(value=dof * nstage / el, unit="DOF-updates/s per RK stage", cores=threads,
+                kind="oracle", single_thread_value=single,
+                sample=f"{nstage} full RK stages of the 32^3 N=3 mesh ({dof} DOF) in {el:.1f} s, "
+                f"torch-CPU float64 on {threads} threads ({platform.machine()}); plus one stage on 1 thread")
+
+
+def kernel_source_hash():
+    """sha256 over the sources the headline stage kernel is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("k_stage.hip", "dg_device.hpp", "dg_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2605_26388_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(bytes_per_launch):
+    """HBM bytes per launch of the headline kernel from the committed counter
+    summary (FETCH_SIZE / WRITE_SIZE KiB per dispatch, scaled by the factors a
+    plain device copy of known size gives); None when the kernel sources have
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "k_stage_euler3d_f64_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        c = json.load(fh)
+    if c.get("source_sha256") != kernel_source_hash():
+        return None
+    t = (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]) * 1024.0
+    return {"bytes_per_launch": t, "over_algorithmic": t / bytes_per_launch}
+
+
+def time_calls(fn, reps, warmup=2):
+    """Mean wall time of fn() (seconds) with the stream synchronised around."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def bench_navier_stokes(reps):
+    from paper_2605_26388_amd import Solver
+    p = di.PRESETS["tgv3d"]
+    out = {}
+    for prec in ("f64", "f32"):
+        s = Solver(3, p["N"], p["nel"], p["lo"], p["hi"], physics="navier_stokes", precision=prec,
+                   mu=p["mu"], prandtl=p["prandtl"])
+        X = s.node_coords().cpu().numpy()
+        U = torch.tensor(di.taylor_green(X, mach=p["mach"]))[None].to(s.device, s.dtype).contiguous()
+        dt = s.dt_cfl(U, p["cfl"])
+        t1, t2 = s.empty(), s.empty()
+        step = time_calls(lambda: s.ssprk3_step(U, dt, t1, t2), reps)
+        dof = s.E * s.Np * s.nv
+        out[prec] = {"ms_per_stage": step / 3 * 1e3, "dof_updates_per_s": 3 * dof / step}
+        s.close()
+    out["workload"] = "tgv3d: Navier-Stokes TGV 16^3, N=4, Re 1600, Mach 0.1, BR1 (two passes per stage)"
+    return out
+
+
+def bench_reacting(reps):
+    from paper_2605_26388_amd import Solver
+    p = di.PRESETS["air5_2d"]
+    mech = di.air5_mechanism(p["mech_seed"])
+    s = Solver(2, 3, p["nel"], p["lo"], p["hi"], physics="reacting", patch_lo=p["patch_lo"],
+               patch_hi=p["patch_hi"], mech=mech)
+    X = s.node_coords().cpu().numpy()
+    U0 = torch.tensor(di.reacting_state(X, p["lo"], p["hi"], mech))[None].to(s.device).contiguous()
+    dt = s.dt_cfl(U0, p["cfl"])
+    nodes = s.E * s.Np
+    U, t1, t2 = U0.clone(), s.empty(), s.empty()
+    stage = time_calls(lambda: s.ssprk3_step(U, dt, t1, t2), reps) / 3
+    out0 = torch.zeros_like(U0)
+    src0 = time_calls(lambda: s.source_chem(U0, out0, 0.0, 0), reps)
+    out1 = s.empty()
+    src1 = time_calls(lambda: s.source_chem(U0, out1, 0.5 * dt, 1), reps)
+    st = s.status()
+    U = U0.clone()
+    strang = time_calls(lambda: s.strang_step(U, dt, t1, t2), max(2, reps // 4))
+    s.close()
+    return {"workload": "air5_2d: reacting Euler 64^2 + 2:1 16^2 patch, N=3, 5-species air, FP64",
+            "stage_ms": stage * 1e3, "source_mode0_node_evals_per_s": nodes / src0,
+            "source_mode1_nodes_per_s": nodes / src1, "newton_iters_max": st["newton_iters_max"],
+            "strang_step_ms": strang * 1e3}
+
+
+def bench_adjoint(steps):
+    """Adjoint workload (16^3, N=3, batch 8) in FP32: forward SSP-RK3 step vs
+    its reverse sweep with stored stage states."""
+    from paper_2605_26388_amd import Solver
+    p = di.PRESETS["adjoint3d"]
+    out = {}
+    for prec in ("f32", "f64"):
+        s = Solver(3, 3, p["nel"], p["lo"], p["hi"], batch=p["batch"], precision=prec)
+        X = s.node_coords().cpu().numpy()
+        base = di.random_euler(X, p["lo"], p["hi"])
+        U = torch.tensor(np.stack([di.perturb_density(base, b) for b in range(p["batch"])]))
+        U = U.to(s.device, s.dtype).contiguous()
+        dt = s.dt_cfl(U, p["cfl"])
+        t1, t2 = s.empty(), s.empty()
+        fwd = time_calls(lambda: s.ssprk3_step(U, dt, t1, t2), steps)
+        bwd_step, _ = time_adjoint(s, U, dt, steps, 2)
+        out[prec] = {"forward_ms_per_step": fwd * 1e3, "backward_ms_per_step": bwd_step * 1e3,
+                     "backward_over_forward": bwd_step / fwd}
+        s.close()
+    out["workload"] = "adjoint3d: 3-D Euler 16^3, N=3, batch 8 (10,485,760 DOF), stored stage states"
+    return out
 
 
 def main():
@@ -135,7 +249,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="euler3d", choices=["euler3d", "euler3d_L"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", choices=["f64", "f32", "adjoint"], default=None,
+    ap.add_argument("--no-extras", action="store_true", help="headline workload only")
+    ap.add_argument("--only", choices=["f64", "f32"], default=None,
                     help="time one form only (profiling runs)")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="instead: run a plain device copy of this many MiB 10 times (counter calibration)")
@@ -159,41 +274,29 @@ def main():
 
     p = di.PRESETS[args.workload]
     res = {}
-    forms = [args.only] if args.only else ["f64", "f32", "adjoint"]
+    forms = [args.only] if args.only else ["f64", "f32"]
     for form in forms:
-        prec = "f32" if form == "f32" else ("f32" if form == "adjoint" else "f64")
+        prec = form
         s = Solver(3, p["N"], p["nel"], p["lo"], p["hi"], precision=prec)
         X = s.node_coords().cpu().numpy()
         U = torch.tensor(di.random_euler(X, p["lo"], p["hi"]))[None].to(s.device, s.dtype).contiguous()
         dt = s.dt_cfl(U, p["cfl"])
         dof = s.E * s.Np * s.nv
-        if form == "adjoint":
-            from paper_2605_26388_amd import DGError
-            st = max(1, args.steps // 2)
-            try:
-                per_step, per_step_ev = time_adjoint(s, U, dt, st, max(1, args.warmup))
-            except DGError as exc:
-                log(f"adjoint not available: {exc}")
-                res[form] = None
-                s.close()
-                continue
-            res[form] = dict(ms_per_step=per_step * 1e3, ms_per_stage=per_step_ev / 3 * 1e3, steps=st)
-            log(f"adjoint FP32: {per_step * 1e3:.3f} ms per step (3 adjoint stages)")
-        else:
-            wall, kern = time_stages(s, U, dt, args.steps, args.warmup)
-            st = s.status()
-            assert st["nonphysical"] == 0, st
-            bytes_per_launch = WORDS_PER_DOF_STAGE * (8 if prec == "f64" else 4) * dof
-            res[form] = dict(wall=wall, kern=kern, dof=dof, bytes=bytes_per_launch,
-                             value=dof * 3 * args.steps / wall, ms_per_step=wall / args.steps * 1e3)
-            log(f"{form}: {wall / args.steps * 1e3:.3f} ms/step, kernel {kern * 1e6:.1f} us/launch, "
-                f"{bytes_per_launch / kern / 1e9:.0f} GB/s algorithmic")
+        wall, kern = time_stages(s, U, dt, args.steps, args.warmup)
+        st = s.status()
+        assert st["nonphysical"] == 0, st
+        bytes_per_launch = WORDS_PER_DOF_STAGE * (8 if prec == "f64" else 4) * dof
+        res[form] = dict(wall=wall, kern=kern, dof=dof, bytes=bytes_per_launch,
+                         value=dof * 3 * args.steps / wall, ms_per_step=wall / args.steps * 1e3)
+        log(f"{form}: {wall / args.steps * 1e3:.3f} ms/step, kernel {kern * 1e6:.1f} us/launch, "
+            f"{bytes_per_launch / kern / 1e9:.0f} GB/s algorithmic")
         s.close()
-
     if args.only:
         return
+
     f64 = res["f64"]
     achieved = f64["bytes"] / f64["kern"] / 1e9
+    traffic = measured_traffic(f64["bytes"])
     out = {
         "metric": "DOF-updates/s per RK stage (FP64 vs FP32 vs adjoint), % HBM roofline",
         "value": f64["value"],
@@ -212,16 +315,22 @@ def main():
                                f"SSP-RK3 at CFL 0.5, FP64",
                    "elements": int(np.prod(p["nel"])), "degree": 3, "dof": f64["dof"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None if traffic is None else traffic["bytes_per_launch"],
+                     "traffic_over_algorithmic": None if traffic is None else traffic["over_algorithmic"],
                      "kernel": "k_stage<3,3,EulerPhys<3>,double>",
                      "kernel_us": f64["kern"] * 1e6, "bytes_per_launch": f64["bytes"]},
         "fp32": {"value": res["f32"]["value"], "kernel_us": res["f32"]["kern"] * 1e6,
                  "speedup_vs_fp64": f64["kern"] / res["f32"]["kern"],
                  "roofline_frac": res["f32"]["bytes"] / res["f32"]["kern"] / 1e9 / HBM_PEAK_GBS},
-        "adjoint": None if res.get("adjoint") is None else {
-            "ms_per_step_fp32": res["adjoint"]["ms_per_step"],
-            "backward_over_forward_fp32": res["adjoint"]["ms_per_step"] / res["f32"]["ms_per_step"]},
     }
+    if not args.no_extras:
+        log("adjoint workload ...")
+        out["adjoint"] = bench_adjoint(max(5, args.steps // 10))
+        log("Navier-Stokes workload ...")
+        out["navier_stokes"] = bench_navier_stokes(max(5, args.steps // 10))
+        log("reacting workload ...")
+        out["reacting"] = bench_reacting(max(5, args.steps // 10))
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(dict(p, N=3))

@@ -164,12 +164,28 @@ k_lam_max(const T* U, int E, int Np, int B, PhysConst pc, double* partial) {
   }
 }
 
-__global__ void k_final_max(const double* partial, int nparts, double* out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double a = 0.0, r = 0.0;
-    for (int j = 0; j < nparts; ++j) {
-      a = partial[2 * j] > a ? partial[2 * j] : a;
-      r = partial[2 * j + 1] > r ? partial[2 * j + 1] : r;
+__global__ void __launch_bounds__(RED_BS) k_final_max(const double* partial, int nparts, double* out) {
+  __shared__ double sh[RED_BS / 64][2];
+  double a = 0.0, r = 0.0;
+  for (int j = threadIdx.x; j < nparts; j += RED_BS) {
+    a = partial[2 * j] > a ? partial[2 * j] : a;
+    r = partial[2 * j + 1] > r ? partial[2 * j + 1] : r;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double x = __shfl_down(a, o, 64), y = __shfl_down(r, o, 64);
+    a = x > a ? x : a;
+    r = y > r ? y : r;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[wid][0] = a;
+    sh[wid][1] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < RED_BS / 64; ++w) {
+      a = sh[w][0] > a ? sh[w][0] : a;
+      r = sh[w][1] > r ? sh[w][1] : r;
     }
     out[0] = a;
     out[1] = r;
@@ -188,7 +204,7 @@ static hipError_t lam_t(const Ctx& c, const void* U, double* d_out, hipStream_t 
     hipLaunchKernelGGL((k_lam_max<T, EulerPhys<3>>), dim3(nb), dim3(RED_BS), 0, s, Ut, c.E, c.Np, c.B, c.pc, c.d_red);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_final_max, dim3(1), dim3(64), 0, s, c.d_red, nb, d_out);
+  hipLaunchKernelGGL(k_final_max, dim3(1), dim3(RED_BS), 0, s, c.d_red, nb, d_out);
   return hipGetLastError();
 }
 

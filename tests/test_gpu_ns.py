@@ -37,8 +37,9 @@ def test_ns_stage_parity_full_workload():
     # At Mach 0.1 the momentum flux carries the mean pressure 1/(gamma M^2),
     # 700 times the pressure variation: rounding in the derivative sweeps
     # (oracle and library alike) is relative to that, so the per-variable
-    # norm is floored at 1e-4 of the flux scale (about 1e-16 of the terms).
-    floor = 1e-4 * flux_scale(op, U)
+    # norm is floored at 1e-3 of the flux scale (the bound is then 1e-15 of
+    # the cancelling terms, about five units in the last place).
+    floor = 1e-3 * flux_scale(op, U)
     dU = s.rhs(Ug)
     assert rel_err_floor(from_gpu(op, dU), op.rhs(U), floor) < 1e-12
     out = s.empty()
