@@ -45,7 +45,10 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
   __shared__ double sRef[F32 ? EPB : 1][DIM][NV];
 
   const int tid = threadIdx.x;
-  for (int q = tid; q < n * n; q += S::BS) sD[q] = dmat_entry<T>(mv.K, q);
+  // the lane's entry of D, stored to LDS only just before the first barrier
+  // (no wait on this load ahead of the state loads)
+  static_assert(n * n <= S::BS, "one D entry per lane");
+  const T dval = tid < n * n ? dmat_entry<T>(mv.K, tid) : T(0);
 
   const int E = mv.E;
   const int nEB = (E + EPB - 1) / EPB;
@@ -58,6 +61,18 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
   const bool active = (tid < S::NT) && (e < E);
   int ec = active ? e : 0;  // clamped for address arithmetic only
   if constexpr (UNIFORM_ELEM) ec = wave_uniform(ec);
+
+  // Per-element tables first, before any store or atomic: with a
+  // wave-uniform element they become scalar loads, and none of them is
+  // waited on in the middle of the computation.
+  const int* nb = mv.nbr + (size_t)ec * 2 * DIM;
+  int nbl[2 * DIM];
+#pragma unroll
+  for (int q = 0; q < 2 * DIM; ++q) nbl[q] = nb[q];
+  double g[DIM];
+#pragma unroll
+  for (int l = 0; l < DIM; ++l) g[l] = mv.geo[(size_t)ec * 4 + l];
+  const double hwinv = 0.5 * mv.K->wend_inv;
 
   int ii[3];
   ii[0] = node % n;
@@ -83,11 +98,10 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
   // is exactly zero and no lane has to branch.
   int side[DIM], nbe[DIM];
   double un[DIM][NV];
-  const int* nb = mv.nbr + (size_t)ec * 2 * DIM;
 #pragma unroll
   for (int l = 0; l < DIM; ++l) {
     side[l] = (ii[l] == 0) ? 0 : ((ii[l] == N) ? 1 : -1);
-    const int lo = nb[2 * l], hi = nb[2 * l + 1];
+    const int lo = nbl[2 * l], hi = nbl[2 * l + 1];
     nbe[l] = side[l] == 0 ? lo : (side[l] == 1 ? hi : ec);
     const bool conf = !MORTAR || nbe[l] >= 0;
     const int ne = conf ? nbe[l] : ec;
@@ -117,6 +131,7 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
   for (int d = 0; d < DIM; ++d) vel[d] = u[MOM + d] * th.ri;
 
   // ---- stage physical fluxes in LDS -------------------------------------
+  if (tid < n * n) sD[tid] = dval;
   if constexpr (F32) {
     if (tid < S::NT && node == 0) {
 #pragma unroll
@@ -143,10 +158,6 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
   }
   __syncthreads();
 
-  double g[DIM];
-#pragma unroll
-  for (int l = 0; l < DIM; ++l) g[l] = mv.geo[(size_t)ec * 4 + l];
-
   // ---- volume integral: -sum_l (2/h_l) sum_m D_im F_l,m ----------------
   double acc[NV];
 #pragma unroll
@@ -159,51 +170,55 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
       const int base = tid - il * st;
       T drow[n];
 #pragma unroll
-      for (int m = 0; m < n; ++m) drow[m] = sD[il * n + m] * static_cast<T>(-g[l]);
+      for (int m = 0; m < n; ++m) drow[m] = sD[il * n + m];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         T s = 0;
 #pragma unroll
         for (int m = 0; m < n; ++m) s = fma(drow[m], sF[l][v][base + m * st], s);
-        acc[v] += static_cast<double>(s);
+        acc[v] = fma(-g[l], static_cast<double>(s), acc[v]);
       }
     }
   }
 
   // ---- surface lift (eq. surf_int) ----------------------------------------
   const double aown = sound<PHYS>(th);
-  const double winv = mv.K->wend_inv;
 #pragma unroll
   for (int l = 0; l < DIM; ++l) {
-    double Fo[NV], Fs[NV];
-    PHYS::flux(u, vel[l], th.p, l, Fo);
-    // Rusanov flux with the element on the -xi_l side as left state, written
-    // in own/neighbour form: the average is symmetric and the jump term
-    // changes sign with the side, both exactly, so the two elements of a
-    // face obtain the same bits.
+    // own physical flux: the FP64 form reads it back from the volume stage
+    double Fo[NV];
+    if constexpr (F32) {
+      PHYS::flux(u, vel[l], th.p, l, Fo);
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Fo[v] = sF[l][v][tid < S::NT ? tid : 0];
+    }
+    // Rusanov flux F* with the element on the -xi_l side as left state,
+    // applied as the difference 2 (F* - F_own) = (F_nb - F_own) - s lam (U_nb - U_own),
+    // s = +1 on the +xi_l face and -1 on the -xi_l face.
     Thermo tn;
     PHYS::thermo(un[l], tn, pc);
     const double vn = un[l][MOM + l] * tn.ri;
-    double Fn[NV];
+    double Fn[NV], Dv[NV];
     PHYS::flux(un[l], vn, tn.p, l, Fn);
     const double co = fabs(vel[l]) + aown;
     const double cn = fabs(vn) + sound<PHYS>(tn);
-    const double hl = 0.5 * (co >= cn ? co : cn);
-    const double hs = side[l] == 1 ? hl : -hl;
+    const double lam = co >= cn ? co : cn;
+    const double hs = side[l] == 1 ? lam : -lam;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Fs[v] = fma(-hs, un[l][v] - u[v], 0.5 * (Fo[v] + Fn[v]));
+    for (int v = 0; v < NV; ++v) Dv[v] = fma(-hs, un[l][v] - u[v], Fn[v] - Fo[v]);
     if constexpr (MORTAR) {
       if (side[l] >= 0 && nbe[l] < 0) {  // 2:1 face: flux from the mortar kernel
         const int row = -nbe[l] - 1;
         const int t = (DIM == 2) ? ii[1 - l] : 0;
         const double* src = mv.mortar_flux + (((size_t)b * mv.nrows + row) * S::NF + t) * NV;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) Fs[v] = src[v];
+        for (int v = 0; v < NV; ++v) Dv[v] = 2.0 * (src[v] - Fo[v]);
       }
     }
-    const double sc = (side[l] == 1 ? -g[l] : g[l]) * winv;
+    const double sc = (side[l] == 1 ? -g[l] : g[l]) * hwinv;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] = fma(sc, Fs[v] - Fo[v], acc[v]);
+    for (int v = 0; v < NV; ++v) acc[v] = fma(sc, Dv[v], acc[v]);
   }
 
   // ---- output ----------------------------------------------------------------

@@ -84,6 +84,27 @@ def test_full_size_workload_parity():
     assert rel_err(from_gpu(op, out), refs) < TOL64
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_stage_parity_large_batched_mesh(precision):
+    """17x16x16 elements at N=3 with a batch of 2 (8704 workgroups, more than
+    the device holds at once): the Shu-Osher stage with distinct U0 per
+    member, in both precisions, against the oracle at the state the kernel
+    reads."""
+    op, s = make_pair(3, 3, (17, 16, 16), (0, 0, 0), (TWO_PI,) * 3, batch=2, precision=precision)
+    U = smooth_euler_state(op, B=2)
+    U0 = smooth_euler_state(op, B=2).flip(0).contiguous()
+    Ug, U0g = to_gpu(s, U), to_gpu(s, U0)
+    out = s.empty()
+    dt = 1e-3
+    s.rk_stage(U0g, Ug, out, 0.75, 0.25, 0.25 * dt)
+    # the oracle at the state the kernel actually reads
+    Uq = from_gpu(op, Ug)
+    U0q = from_gpu(op, U0g)
+    ref = rk_stage(op, U0q, Uq, 0.75, 0.25, 0.25 * dt)
+    tol = TOL64 if precision == "f64" else 1e-6
+    assert rel_err(from_gpu(op, out), ref) < tol
+
+
 def test_large_workload_invariants():
     """64^3: free stream is preserved and the RHS is conservative."""
     p = di.PRESETS["euler3d_L"]
