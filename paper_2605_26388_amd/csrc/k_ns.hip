@@ -74,7 +74,9 @@ k_ns(StageParams sp, MeshView mv, PhysConst pc, T* face) {
   __shared__ double sD[n * n];
 
   const int tid = threadIdx.x;
-  for (int q = tid; q < n * n; q += S::BS) sD[q] = mv.K->D[q];
+  // the lane's entry of D, written to LDS only before the first barrier
+  static_assert(n * n <= S::BS, "one D entry per lane");
+  const double dval = tid < n * n ? mv.K->D[tid] : 0.0;
 
   const int E = mv.E;
   const int nEB = (E + EPB - 1) / EPB;
@@ -92,6 +94,17 @@ k_ns(StageParams sp, MeshView mv, PhysConst pc, T* face) {
   ii[2] = node / (n * n);
   const int stride[3] = {1, n, n * n};
 
+  // Element tables before any store or atomic (scalar loads, no mid-kernel
+  // waits): neighbours, scales 2/h, 1/w_end.
+  const int* nb = mv.nbr + (size_t)ec * 6;
+  int nbl[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) nbl[q] = nb[q];
+  double g[3];
+#pragma unroll
+  for (int l = 0; l < 3; ++l) g[l] = mv.geo[(size_t)ec * 4 + l];
+  const double winv = mv.K->wend_inv;
+
   const size_t plane = (size_t)E * NP;
   const size_t pbytes = plane * sizeof(T);
   const T* Ub = static_cast<const T*>(sp.Uk) + (size_t)b * NV * plane;
@@ -105,11 +118,10 @@ k_ns(StageParams sp, MeshView mv, PhysConst pc, T* face) {
 
   int side[3], nbe[3];
   double un[3][NV];
-  const int* nb = mv.nbr + (size_t)ec * 6;
 #pragma unroll
   for (int l = 0; l < 3; ++l) {
     side[l] = (ii[l] == 0) ? 0 : ((ii[l] == N) ? 1 : -1);
-    nbe[l] = (active && side[l] >= 0) ? nb[2 * l + side[l]] : -1;
+    nbe[l] = (active && side[l] >= 0) ? nbl[2 * l + side[l]] : -1;
     if (nbe[l] >= 0) {
       const unsigned noff = (unsigned)(nbe[l] * NP + node + (side[l] ? -N : N) * stride[l]);
 #pragma unroll
@@ -131,16 +143,12 @@ k_ns(StageParams sp, MeshView mv, PhysConst pc, T* face) {
   const double kc = pc.gamma * pc.mu / (pc.prandtl * gm1);
   double W[4];
   prim_w(u, gm1, W);
+  if (tid < n * n) sD[tid] = dval;
   if (tid < S::NT) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) sW[q][tid] = W[q];
   }
   __syncthreads();
-
-  double g[3];
-#pragma unroll
-  for (int l = 0; l < 3; ++l) g[l] = mv.geo[(size_t)ec * 4 + l];
-  const double winv = mv.K->wend_inv;
 
   // ---- lifted gradient S[l][q] = dW_q / dx_l --------------------------------
   double Sg[3][4];
@@ -192,6 +200,23 @@ k_ns(StageParams sp, MeshView mv, PhysConst pc, T* face) {
     }
     return;
   } else {
+    // The two buffered viscous face fluxes per face direction, fetched now so
+    // that their latency hides behind the volume terms.  A lane not on a face
+    // in direction l reads the same value twice, which makes its viscous
+    // face correction exactly zero.
+    double fvo[3][4], fvn[3][4];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      const int q = face_node<n>(ii, l);
+      const bool f = nbe[l] >= 0;
+      const size_t own = ((((size_t)b * E + ec) * 6 + 2 * l + (side[l] > 0 ? 1 : 0)) * NF + q) * 4;
+      const size_t oth = f ? ((((size_t)b * E + nbe[l]) * 6 + 2 * l + 1 - side[l]) * NF + q) * 4 : own;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        fvo[l][c] = static_cast<double>(face[own + c]);
+        fvn[l][c] = static_cast<double>(face[oth + c]);
+      }
+    }
     // ---- combined flux G^l = F_inv^l - F_v^l in LDS -------------------------
     Thermo th;
     const bool ok = PHYS::thermo(u, th, pc);
@@ -239,7 +264,10 @@ k_ns(StageParams sp, MeshView mv, PhysConst pc, T* face) {
 #pragma unroll
       for (int l = 0; l < 3; ++l) {
         if (side[l] < 0) continue;
-        double Fo[NV], Fn[NV], Fs[NV];
+        // Rusanov as a difference to the own flux, 2 (F* - F_own) =
+        // (F_nb - F_own) - s lam (U_nb - U_own), s = +1 on the +xi_l face;
+        // the central viscous flux likewise, 2 ({{F_v}} - F_v,own) = F_v,nb - F_v,own.
+        double Fo[NV], Fn[NV], Dv[NV];
         PHYS::flux(u, vel[l], th.p, l, Fo);
         Thermo tn;
         PHYS::thermo(un[l], tn, pc);
@@ -247,23 +275,14 @@ k_ns(StageParams sp, MeshView mv, PhysConst pc, T* face) {
         PHYS::flux(un[l], vn, tn.p, l, Fn);
         const double co = fabs(vel[l]) + aown;
         const double cn = fabs(vn) + sound<PHYS>(tn);
-        const double hl = 0.5 * (co >= cn ? co : cn);
-        const double hs = side[l] ? hl : -hl;
+        const double lam = co >= cn ? co : cn;
+        const double hs = side[l] ? lam : -lam;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) Fs[v] = fma(-hs, un[l][v] - u[v], 0.5 * (Fo[v] + Fn[v]));
-        // central viscous flux from the two buffered face values
-        const int q = face_node<n>(ii, l);
-        const T* own = face + ((((size_t)b * E + e) * 6 + 2 * l + side[l]) * NF + q) * 4;
-        const T* oth = face + ((((size_t)b * E + nbe[l]) * 6 + 2 * l + 1 - side[l]) * NF + q) * 4;
-        const double sc = (side[l] ? -g[l] : g[l]) * winv;
-        acc[0] = fma(sc, Fs[0] - Fo[0], acc[0]);
+        for (int v = 0; v < NV; ++v) Dv[v] = fma(-hs, un[l][v] - u[v], Fn[v] - Fo[v]);
+        const double sc = (side[l] ? -g[l] : g[l]) * (0.5 * winv);
+        acc[0] = fma(sc, Dv[0], acc[0]);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const double fo = static_cast<double>(own[c]);
-          const double fv = 0.5 * (fo + static_cast<double>(oth[c]));
-          // combined jump: (F* - F) - (Fv* - Fv)
-          acc[1 + c] = fma(sc, (Fs[1 + c] - Fo[1 + c]) - (fv - fo), acc[1 + c]);
-        }
+        for (int c = 0; c < 4; ++c) acc[1 + c] = fma(sc, Dv[1 + c] - (fvn[l][c] - fvo[l][c]), acc[1 + c]);
       }
     }
     if (active) {
