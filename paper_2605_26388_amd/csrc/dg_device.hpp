@@ -84,27 +84,23 @@ template <> struct Buf<float> {
 // is uniform across the wave).
 __device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
-// Reciprocal and square root for the hot loops: hardware estimate refined by
-// Newton-Raphson (reciprocal) and the coupled Goldschmidt iteration (square
-// root, Markstein's formulation), accurate to about one unit in the last
-// place for the normal-range positive operands met here.  Both are plain
-// sequences of fma, so every call site rounds identically.
+// Reciprocal and square root for the hot loops, from the hardware estimates
+// (relative error about 2^-24) refined in FMA chains: the reciprocal by one
+// Newton-Raphson step (at most 11 units in the last place, measured over 2^20
+// operands in [1e-3, 1e3]); the square root by one step of the coupled
+// Goldschmidt iteration (Markstein's formulation) and one residual
+// correction (at most 0.5 units in the last place on the same operands).
+// Plain sequences of fma: every call site rounds identically.
 __device__ __forceinline__ double frcp(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
 }
 
 __device__ __forceinline__ double fsqrt(double x) {
   const double y = __builtin_amdgcn_rsq(x);
   double g = x * y;
   double h = 0.5 * y;
-  double r = fma(-g, h, 0.5);
-  g = fma(g, r, g);
-  h = fma(h, r, h);
-  r = fma(-g, h, 0.5);
+  const double r = fma(-g, h, 0.5);
   g = fma(g, r, g);
   h = fma(h, r, h);
   const double d = fma(-g, g, x);
