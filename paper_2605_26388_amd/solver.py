@@ -77,6 +77,7 @@ class Solver:
         check(self.lib.dg_sizes(ctx, ctypes.byref(E), ctypes.byref(Np), ctypes.byref(nv)), "dg_sizes")
         self.E, self.Np, self.nv = E.value, Np.value, nv.value
         self.shape = (self.batch, self.nv, self.E, self.Np)
+        self._numel = self.batch * self.nv * self.E * self.Np
 
     # -- helpers ---------------------------------------------------------------
     def close(self):
@@ -98,7 +99,7 @@ class Solver:
             return None
         if not isinstance(t, torch.Tensor) or t.device != self.device:
             raise ValueError(f"{name}: expected a tensor on {self.device}")
-        if t.dtype != self.dtype or not t.is_contiguous() or t.numel() != int(np.prod(self.shape)):
+        if t.dtype != self.dtype or not t.is_contiguous() or t.numel() != self._numel:
             raise ValueError(f"{name}: expected a contiguous {self.dtype} tensor of shape {self.shape}")
         return ctypes.c_void_p(t.data_ptr())
 
