@@ -170,12 +170,13 @@ def time_calls(fn, reps, warmup=2):
     return (time.perf_counter() - t0) / reps
 
 
-def bench_navier_stokes(reps):
+def bench_navier_stokes(reps, nel=None):
     from paper_2605_26388_amd import Solver
     p = di.PRESETS["tgv3d"]
+    nel = tuple(nel) if nel else tuple(p["nel"])
     out = {}
     for prec in ("f64", "f32"):
-        s = Solver(3, p["N"], p["nel"], p["lo"], p["hi"], physics="navier_stokes", precision=prec,
+        s = Solver(3, p["N"], nel, p["lo"], p["hi"], physics="navier_stokes", precision=prec,
                    mu=p["mu"], prandtl=p["prandtl"])
         X = s.node_coords().cpu().numpy()
         U = torch.tensor(di.taylor_green(X, mach=p["mach"]))[None].to(s.device, s.dtype).contiguous()
@@ -185,7 +186,7 @@ def bench_navier_stokes(reps):
         dof = s.E * s.Np * s.nv
         out[prec] = {"ms_per_stage": step / 3 * 1e3, "dof_updates_per_s": 3 * dof / step}
         s.close()
-    out["workload"] = "tgv3d: Navier-Stokes TGV 16^3, N=4, Re 1600, Mach 0.1, BR1 (two passes per stage)"
+    out["workload"] = (f"tgv3d: Navier-Stokes TGV {nel[0]}^3, N=4, Re 1600, Mach 0.1, BR1 (two passes per stage)")
     return out
 
 
@@ -248,6 +249,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--only", choices=["f64", "f32"], default=None,
                     help="time one form only (profiling runs)")
+    ap.add_argument("--side", choices=["adjoint", "navier_stokes", "navier_stokes_L", "reacting"], default=None,
+                    help="instead: run one side workload alone and print its JSON (profiling runs)")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="instead: run a plain device copy of this many MiB 10 times (counter calibration)")
     args = ap.parse_args()
@@ -264,6 +267,15 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         log(f"copied {args.calib_copy} MiB x 10")
+        return
+
+    if args.side:
+        reps = max(5, args.steps // 10)
+        fn = {"adjoint": lambda: bench_adjoint(reps),
+              "navier_stokes": lambda: bench_navier_stokes(reps),
+              "navier_stokes_L": lambda: bench_navier_stokes(reps, nel=(32, 32, 32)),
+              "reacting": lambda: bench_reacting(reps)}[args.side]
+        print(json.dumps({args.side: fn()}), flush=True)
         return
 
     from paper_2605_26388_amd import Solver
