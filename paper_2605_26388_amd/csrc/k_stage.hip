@@ -49,6 +49,7 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
   constexpr bool F32 = std::is_same<T, float>::value;
   // an element fills whole waves: its index and tables are wave-uniform
   constexpr bool UNIFORM_ELEM = (NP % 64) == 0;
+  constexpr bool MASK_FACES = !F32 && !MORTAR;
 
   __shared__ T sF[DIM][NV][EPB * NP];
   __shared__ T sD[n * n];
@@ -105,7 +106,12 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
   // Neighbour's matching node for each direction.  A lane that is not on a
   // face in direction l uses its own node: the interface flux of a state
   // with itself is its physical flux, so that direction's correction below
-  // is exactly zero and no lane has to branch.
+  // is exactly zero and no lane has to branch.  The FP64 form on conforming
+  // meshes instead masks such lanes out of that direction's loads and face
+  // arithmetic: idle lanes draw less power, which at the board power limit
+  // the device sustains under this kernel is worth more than the uniform
+  // control flow (measured; the FP32 form measures the other way, and the
+  // mortar form would spill registers).
   int side[DIM], nbe[DIM];
   double un[DIM][NV];
 #pragma unroll
@@ -117,8 +123,13 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
     const int ne = conf ? nbe[l] : ec;
     const int shift = side[l] == 1 ? -N : (side[l] == 0 ? N : 0);
     const unsigned noff = (unsigned)(ne * NP + node + shift * stride[l]);
+    if (!MASK_FACES || side[l] >= 0) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) un[l][v] = Buf<T>::load(rU, noff, v * pstride);
+      for (int v = 0; v < NV; ++v) un[l][v] = Buf<T>::load(rU, noff, v * pstride);
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) un[l][v] = 0.0;
+    }
   }
   // stage input U0, fetched early as well
   const bool use_u0 = (sp.mode != 0) && (sp.a != 0.0);
@@ -195,6 +206,7 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
   const double aown = wave_sound<PHYS, F32>(th);
 #pragma unroll
   for (int l = 0; l < DIM; ++l) {
+    if (MASK_FACES && side[l] < 0) continue;  // masked lane: no face in direction l
     // own physical flux: the FP64 form reads it back from the volume stage
     double Fo[NV];
     if constexpr (F32) {
