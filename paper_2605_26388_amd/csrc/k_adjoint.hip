@@ -74,7 +74,9 @@ k_adjoint(AdjParams ap, MeshView mv, PhysConst pc) {
   __shared__ T sDt[n * n];
 
   const int tid = threadIdx.x;
-  for (int q = tid; q < n * n; q += S::BS) sDt[q] = static_cast<T>(mv.K->Dt[q]);
+  // the lane's entry of D^T, written to LDS only before the first barrier
+  static_assert(n * n <= S::BS, "one D entry per lane");
+  const T dtval = tid < n * n ? static_cast<T>(mv.K->Dt[tid]) : T(0);
 
   const int E = mv.E;
   const int nEB = (E + EPB - 1) / EPB;
@@ -86,6 +88,16 @@ k_adjoint(AdjParams ap, MeshView mv, PhysConst pc) {
   const int e = eb * EPB + el;
   const bool active = (tid < S::NT) && (e < E);
   const int ec = active ? e : 0;
+  // element tables first (scalar loads for a wave-uniform element, never
+  // waited on in the middle of the computation)
+  const int* nb = mv.nbr + (size_t)ec * 2 * DIM;
+  int nbl[2 * DIM];
+#pragma unroll
+  for (int q = 0; q < 2 * DIM; ++q) nbl[q] = nb[q];
+  double g[DIM];
+#pragma unroll
+  for (int l = 0; l < DIM; ++l) g[l] = mv.geo[(size_t)ec * 4 + l];
+  const double winv = mv.K->wend_inv;
   int ii[3];
   ii[0] = node % n;
   ii[1] = (node / n) % n;
@@ -110,11 +122,10 @@ k_adjoint(AdjParams ap, MeshView mv, PhysConst pc) {
   }
   int side[DIM], nbe[DIM];
   double un[DIM][NV], ln[DIM][NV];
-  const int* nb = mv.nbr + (size_t)ec * 2 * DIM;
 #pragma unroll
   for (int l = 0; l < DIM; ++l) {
     side[l] = (ii[l] == 0) ? 0 : ((ii[l] == N) ? 1 : -1);
-    nbe[l] = (active && side[l] >= 0) ? nb[2 * l + side[l]] : -1;
+    nbe[l] = (active && side[l] >= 0) ? nbl[2 * l + side[l]] : -1;
     if (nbe[l] >= 0) {
       const unsigned noff = (unsigned)(nbe[l] * NP + node + (side[l] ? -N : N) * stride[l]);
 #pragma unroll
@@ -139,16 +150,13 @@ k_adjoint(AdjParams ap, MeshView mv, PhysConst pc) {
 #pragma unroll
   for (int d = 0; d < DIM; ++d) vel[d] = u[1 + d] * th.ri;
 
+  if (tid < n * n) sDt[tid] = dtval;
   if (tid < S::NT) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) sL[v][tid] = static_cast<T>(lam[v]);
   }
   __syncthreads();
 
-  double g[DIM];
-#pragma unroll
-  for (int l = 0; l < DIM; ++l) g[l] = mv.geo[(size_t)ec * 4 + l];
-  const double winv = mv.K->wend_inv;
   const double gamma = pc.gamma;
   double aown = 0.0;
   bool on_face = false;
