@@ -41,8 +41,16 @@ __device__ __forceinline__ double wave_sound(const Thermo& t) {
   else return sound<PHYS>(t);
 }
 
+// register budget: four waves per SIMD; the reacting physics (eight
+// variables, mortar faces, 77,824-node workloads) takes three, which it needs
+// to keep its face state in registers
+template <class PHYS>
+struct StageWaves {
+  static constexpr int value = PHYS::NV > 5 ? 3 : 4;
+};
+
 template <int DIM, int N, class PHYS, typename T, bool MORTAR>
-__global__ void __launch_bounds__((Shape<DIM, N>::BS)) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__((Shape<DIM, N>::BS)) __attribute__((amdgpu_waves_per_eu(StageWaves<PHYS>::value)))
 k_stage(StageParams sp, MeshView mv, PhysConst pc) {
   using S = Shape<DIM, N>;
   constexpr int n = S::n, NP = S::NP, EPB = S::EPB, NV = PHYS::NV, MOM = PHYS::MOM;
