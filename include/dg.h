@@ -120,7 +120,12 @@ typedef struct dg_counters {
 typedef struct dg_ctx dg_ctx;
 
 /* Build a context: mesh tables, reference-element constants, mortar
- * operators and mechanism on the device.  Synchronous; allocates. */
+ * operators and mechanism on the device.  Synchronous; allocates.
+ * Size limit: the kernels address one batch member's state (nvars * E * Np
+ * values of the context precision) with 32-bit byte offsets, so that block
+ * must stay below 4 GiB (3-D, N = 3, FP64: at most 1,677,721 elements per
+ * member); larger meshes are rejected with DG_ERR_UNSUPPORTED, as are
+ * element counts beyond the int32 range. */
 int dg_create(const dg_desc* desc, dg_ctx** out);
 int dg_destroy(dg_ctx* ctx);
 

@@ -422,6 +422,18 @@ int dg_create(const dg_desc* desc, dg_ctx** out) {
     if (!(d.hi[l] > d.lo[l])) return fail(DG_ERR_ARG, "hi must exceed lo");
   }
   if (!(d.gamma > 1.0) && d.physics != DG_REACTING_EULER) return fail(DG_ERR_ARG, "gamma must exceed 1");
+  {
+    // one batch member's state is addressed with 32-bit byte offsets
+    const long double n1 = d.degree + 1.0L;
+    long double elems = 1.0L;
+    for (int l = 0; l < d.dim; ++l) elems *= d.nel[l];
+    if (d.dim == 2 && (d.patch_lo[0] != d.patch_hi[0] || d.patch_lo[1] != d.patch_hi[1]))
+      elems += 3.0L * (d.patch_hi[0] - d.patch_lo[0]) * (d.patch_hi[1] - d.patch_lo[1]);
+    const int nvars = d.physics == DG_REACTING_EULER ? (d.mech ? d.mech->nspecies : 0) + d.dim + 1 : d.dim + 2;
+    const long double bytes = elems * (d.dim == 3 ? n1 * n1 * n1 : n1 * n1) * nvars * (d.precision == DG_F32 ? 4 : 8);
+    if (elems > 2147483647.0L || bytes >= 4294967296.0L)
+      return fail(DG_ERR_UNSUPPORTED, "one batch member's state must stay below 4 GiB (32-bit addressing)");
+  }
   const bool patch = d.dim == 2 && (d.patch_lo[0] != d.patch_hi[0] || d.patch_lo[1] != d.patch_hi[1]);
   if (patch) {
     for (int l = 0; l < 2; ++l)
