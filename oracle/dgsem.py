@@ -120,14 +120,8 @@ class Operator:
     def rhs_inviscid(self, U, form="strong"):
         ph, dim, N = self.phys, self.dim, self.N
         P = ph.prims(U)
-        J = self.per_elem(self.J)
-        dU = torch.zeros_like(U)
-        F = []
-        for l in range(dim):
-            Ft = self.per_elem(self.Ja[l]) * ph.flux(U, l, P)   # contravariant flux
-            F.append(Ft)
-            Dop = self.D if form == "strong" else self.Dhat
-            dU = dU - dsweep(Ft, Dop, dim, l) / J
+        F = [self.per_elem(self.Ja[l]) * ph.flux(U, l, P) for l in range(dim)]   # contravariant fluxes
+        dU = self.volume_term(U, F, form)
         strong = 1.0 if form == "strong" else 0.0
         shape = U.shape
         # conforming interfaces
@@ -152,6 +146,15 @@ class Operator:
         # 2:1 mortars
         if self.mesh.mortars:
             dU = dU + self.mortar_terms(U, F, strong)
+        return dU
+
+    def volume_term(self, U, F, form):
+        """-(1/J) sum_l D Ft^l (eq. vol_weak), or its weak-form counterpart."""
+        J = self.per_elem(self.J)
+        dU = torch.zeros_like(U)
+        Dop = self.D if form == "strong" else self.Dhat
+        for l in range(self.dim):
+            dU = dU - dsweep(F[l], Dop, self.dim, l) / J
         return dU
 
     def mortar_terms(self, U, F, strong):
