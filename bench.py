@@ -31,6 +31,23 @@ sys.path.insert(0, ROOT)
 import dginputs as di  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFS = 78.6
+
+
+def split_flops_per_element(dim, N):
+    """Algorithmic FP64 operations of the split-form volume sum of one
+    element (an FMA counts 2): one two-point flux per unordered node pair of
+    every line (the flux is symmetric), each pair adding D_im F# to node i and
+    D_mi F# to node m.  The flux as evaluated: two log means (30 and 25
+    operations: sum, difference, a reciprocal of 5, the degree-7 series, a
+    second reciprocal or the products), arithmetic means and v_i . v_m
+    (4 dim - 1), and the rows (13 + dim), i.e. 67 + 5 dim; plus 2 x (dim + 2)
+    FMAs of accumulation."""
+    n = N + 1
+    flux = 67 + 5 * dim
+    acc = 2 * 2 * (dim + 2)
+    lines = dim * n ** (dim - 1)
+    return lines * (n * (n - 1) // 2) * (flux + acc)
 # Algorithmic state traffic of one SSP-RK3 step: stage 1 reads U^n and writes
 # U1, stages 2 and 3 read U^n and U_k and write U_(k+1): 8 arrays over 3
 # stages, i.e. 8/3 words per DOF per stage on average.
@@ -245,6 +262,39 @@ def bench_reacting(reps):
             "strang_step_ms": strang * 1e3}
 
 
+def bench_split(steps, warmup):
+    """Split-form stage (entropy-conservative volume integral, Ranocha flux)
+    on the headline workload, FP64 and FP32 storage: the kernel's mean launch
+    time, its throughput, and its ALU roofline (algorithmic FP64 operations
+    per launch over the launch time, against the FP64 vector peak)."""
+    from paper_2605_26388_amd import Solver
+    p = di.PRESETS["euler3d"]
+    out = {}
+    for prec in ("f64", "f32"):
+        s = Solver(3, p["N"], p["nel"], p["lo"], p["hi"], precision=prec, volume="split")
+        X = s.node_coords().cpu().numpy()
+        U = torch.tensor(di.random_euler(X, p["lo"], p["hi"]))[None].to(s.device, s.dtype).contiguous()
+        dt = s.dt_cfl(U, p["cfl"])
+        wall, kern = time_stages(s, U, dt, steps, warmup)
+        st = s.status()
+        assert st["nonphysical"] == 0, st
+        dof = s.E * s.Np * s.nv
+        flops = split_flops_per_element(3, p["N"]) * s.E
+        achieved = flops / kern / 1e12
+        out[prec] = {"kernel_us": kern * 1e6, "value": dof * 3 * steps / wall,
+                     "ms_per_step": wall / steps * 1e3,
+                     "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFS,
+                                  "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFS,
+                                  "flops_per_launch": flops},
+                     "hbm_frac": WORDS_PER_DOF_STAGE * (8 if prec == "f64" else 4) * dof / kern / 1e9
+                     / HBM_PEAK_GBS}
+        log(f"split {prec}: kernel {kern * 1e6:.1f} us/launch, {achieved:.2f} TFLOP/s algorithmic")
+        s.close()
+    out["workload"] = ("euler3d split form: 3-D Euler 32^3, N=3, entropy-conservative volume integral "
+                       "(Ranocha flux), Rusanov interfaces, SSP-RK3 at CFL 0.5")
+    return out
+
+
 def bench_adjoint(steps):
     """Adjoint workload (16^3, N=3, batch 8) in FP32: forward SSP-RK3 step vs
     its reverse sweep with stored stage states."""
@@ -280,7 +330,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--only", choices=["f64", "f32"], default=None,
                     help="time one form only (profiling runs)")
-    ap.add_argument("--side", choices=["adjoint", "navier_stokes", "navier_stokes_L", "reacting"], default=None,
+    ap.add_argument("--side", choices=["adjoint", "navier_stokes", "navier_stokes_L", "reacting", "split"],
+                    default=None,
                     help="instead: run one side workload alone and print its JSON (profiling runs)")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="instead: run a plain device copy of this many MiB 10 times (counter calibration)")
@@ -305,7 +356,8 @@ def main():
         fn = {"adjoint": lambda: bench_adjoint(reps),
               "navier_stokes": lambda: bench_navier_stokes(reps),
               "navier_stokes_L": lambda: bench_navier_stokes(reps, nel=(32, 32, 32)),
-              "reacting": lambda: bench_reacting(reps)}[args.side]
+              "reacting": lambda: bench_reacting(reps),
+              "split": lambda: bench_split(args.steps, args.warmup)}[args.side]
         print(json.dumps({args.side: fn()}), flush=True)
         return
 
@@ -370,6 +422,8 @@ def main():
         out["navier_stokes"] = bench_navier_stokes(max(5, args.steps // 10))
         log("reacting workload ...")
         out["reacting"] = bench_reacting(max(5, args.steps // 10))
+        log("split-form workload ...")
+        out["split"] = bench_split(args.steps, args.warmup)
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(dict(p, N=3))

@@ -65,6 +65,16 @@ enum dg_status {
 enum dg_physics { DG_EULER = 0, DG_NAVIER_STOKES = 1, DG_REACTING_EULER = 2 };
 enum dg_precision { DG_F64 = 0, DG_F32 = 1 };
 
+/* Volume integral of the Euler operator.
+ * DG_VOLUME_STANDARD: strong form of eq. vol_weak, sum_m D_im F_l(U_m).
+ * DG_VOLUME_SPLIT: entropy-conservative split form (eq. vol_split, the
+ *   appendix on the inviscid volume flux): 2 sum_m D_im F#_l(U_i, U_m) with
+ *   Ranocha's kinetic-energy-preserving, entropy-conservative two-point flux
+ *   in its published form (the energy row as printed in the paper is not
+ *   entropy conservative), logarithmic means of rho and rho/p.  Euler
+ *   physics only; the interface flux stays Rusanov; no adjoint. */
+enum dg_volume { DG_VOLUME_STANDARD = 0, DG_VOLUME_SPLIT = 1 };
+
 /* Reaction mechanism (Source Terms section; finite-rate appendix).
  * Species data per unit mass (SI); rate constants k = A T^beta exp(-Theta/T)
  * in the units implied by kappa_c: concentrations [X_s] = kappa_c rho_s/W_s,
@@ -105,6 +115,7 @@ typedef struct dg_desc {
   int32_t newton_max_iter; /* implicit source substep, default 25 if <= 0 */
   double newton_tol;       /* stop when max |dY| <= tol * rho, default 1e-13 */
   int32_t device;          /* HIP device ordinal the context lives on */
+  int32_t volume;          /* dg_volume; 0 (standard) when zero-initialised */
 } dg_desc;
 
 /* Sticky device-side counters (dg_status_read). */

@@ -17,6 +17,7 @@ DG_MAX_REACTIONS = 8
 DG_OK, DG_ERR_ARG, DG_ERR_UNSUPPORTED, DG_ERR_HIP, DG_ERR_OOM, DG_ERR_NONPHYSICAL, DG_ERR_NEWTON = range(7)
 DG_EULER, DG_NAVIER_STOKES, DG_REACTING_EULER = range(3)
 DG_F64, DG_F32 = range(2)
+DG_VOLUME_STANDARD, DG_VOLUME_SPLIT = range(2)
 
 EXPORTS = (
     "dg_create", "dg_destroy", "dg_sizes", "dg_node_coords", "dg_rhs", "dg_rk_stage",
@@ -50,6 +51,7 @@ class Desc(ctypes.Structure):
         ("gamma", c_double), ("mu", c_double), ("prandtl", c_double),
         ("mech", POINTER(Mechanism)),
         ("newton_max_iter", c_int32), ("newton_tol", c_double), ("device", c_int32),
+        ("volume", c_int32),
     ]
 
 

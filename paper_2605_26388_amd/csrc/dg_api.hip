@@ -457,6 +457,10 @@ int dg_create(const dg_desc* desc, dg_ctx** out) {
       break;
     default: return fail(DG_ERR_ARG, "unknown physics");
   }
+  if (d.volume != DG_VOLUME_STANDARD && d.volume != DG_VOLUME_SPLIT)
+    return fail(DG_ERR_ARG, "volume must be DG_VOLUME_STANDARD or DG_VOLUME_SPLIT");
+  if (d.volume == DG_VOLUME_SPLIT && d.physics != DG_EULER)
+    return fail(DG_ERR_UNSUPPORTED, "split-form volume integral: Euler physics only");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(DG_ERR_HIP, "no HIP device");
   if (d.device < 0 || d.device >= ndev) return fail(DG_ERR_ARG, "device ordinal out of range");
@@ -632,6 +636,8 @@ int dg_rhs_adjoint(dg_ctx* ctx, const void* U, const void* lam_L, void* lam_U, v
   Ctx& c = ctx->c;
   if (c.desc.physics != DG_EULER || c.nmortar > 0 || c.N > 4)
     return fail(DG_ERR_UNSUPPORTED, "adjoint: Euler physics on conforming meshes, degree <= 4");
+  if (c.desc.volume != DG_VOLUME_STANDARD)
+    return fail(DG_ERR_UNSUPPORTED, "adjoint: standard volume integral only");
   const size_t bytes = state_bytes(c);
   if (overlaps(lam_U, U, bytes) || overlaps(lam_U, lam_L, bytes))
     return fail(DG_ERR_ARG, "dg_rhs_adjoint: lam_U aliases an input");
@@ -646,6 +652,8 @@ int dg_rk_stage_adjoint(dg_ctx* ctx, const void* Uk, const void* lam_out, void* 
   Ctx& c = ctx->c;
   if (c.desc.physics != DG_EULER || c.nmortar > 0 || c.N > 4)
     return fail(DG_ERR_UNSUPPORTED, "adjoint: Euler physics on conforming meshes, degree <= 4");
+  if (c.desc.volume != DG_VOLUME_STANDARD)
+    return fail(DG_ERR_UNSUPPORTED, "adjoint: standard volume integral only");
   if (lam0_mode != DG_LAM0_ACCUMULATE && lam0_mode != DG_LAM0_FOLD && lam0_mode != DG_LAM0_INIT)
     return fail(DG_ERR_ARG, "dg_rk_stage_adjoint: unknown lam0_mode");
   const size_t bytes = state_bytes(c);

@@ -15,6 +15,15 @@
 //      mortar faces take the flux from the mortar kernel's rows instead;
 //   4. write dU/dt, or the stage a U0 + b U_k + c dU/dt.
 //
+// Split form (eq. vol_split): instead of fluxes the block stages primitives
+// (rho, v, p, rho/p and the logarithms of rho and rho/p) in LDS, and each lane sums 2 D_im F#_l(U_i, U_m) over
+// the other nodes m of its line with Ranocha's two-point flux (published
+// form: log means of rho and rho/p, arithmetic means of v and p, the crossed
+// pressure-velocity product in the energy row).  The m = i term, D_ii F_l(U_i),
+// is nonzero only at the line's end nodes (GLL: D_ii = 0 inside), so it is
+// added in the face step, which computes F_l(U_i) there anyway.  Faces, lift
+// and output are those of the standard form.
+//
 // FP32 form: states and the LDS flux operand are float, the D-sweep is a
 // float FMA chain.  Primitive recovery, flux evaluation and the face
 // corrections (F* - F) stay in double; before rounding to float the volume
@@ -41,16 +50,152 @@ __device__ __forceinline__ double wave_sound(const Thermo& t) {
   else return sound<PHYS>(t);
 }
 
+// Logarithmic mean {{x}}_ln = (x - y) / (ln x - ln y) of positive x, y and its
+// reciprocal.  With f = (x - y)/(x + y) and u = f^2, ln(x/y) = 2 atanh f =
+// 2 f P(u), P(u) = sum_k u^k / (2k + 1), hence {{x}}_ln = (x + y) / (2 P(u)):
+// no cancellation as x -> y, and the limit x at x = y comes out exactly.  For
+// u < 1e-2 (x/y within about 1.22) P summed through u^7 leaves a relative
+// truncation below u^8/17 < 6e-18.  The fast form uses the series for every
+// pair and raises `far` where u >= 1e-2; the exact form takes the closed
+// form there, with ln x and ln y computed once per node and read from LDS.
+// Branches inside the unrolled sweep would make it spill registers, so a
+// lane that raised `far` redoes its whole volume sum in the exact form (a
+// path smooth states never take).
+__device__ __forceinline__ double atanh_ratio_series(double u) {
+  double P = 1.0 / 15.0;
+  P = fma(P, u, 1.0 / 13.0);
+  P = fma(P, u, 1.0 / 11.0);
+  P = fma(P, u, 1.0 / 9.0);
+  P = fma(P, u, 1.0 / 7.0);
+  P = fma(P, u, 1.0 / 5.0);
+  P = fma(P, u, 1.0 / 3.0);
+  return fma(P, u, 1.0);
+}
+
+template <bool EXACT>
+__device__ __forceinline__ double log_mean(double x, double y, const double* lnx, const double* lny, bool& far) {
+  const double s = x + y, d = x - y;
+  const double f = d * frcp(s);
+  const double u = f * f;
+  double r = 0.5 * s * frcp(atanh_ratio_series(u));
+  if constexpr (EXACT) {
+    if (u >= 1e-2) r = d / (*lnx - *lny);
+  } else {
+    far |= u >= 1e-2;
+  }
+  return r;
+}
+
+template <bool EXACT>
+__device__ __forceinline__ double inv_log_mean(double x, double y, const double* lnx, const double* lny, bool& far) {
+  const double s = x + y, d = x - y;
+  const double rs = frcp(s);
+  const double f = d * rs;
+  const double u = f * f;
+  double r = 2.0 * atanh_ratio_series(u) * rs;
+  if constexpr (EXACT) {
+    if (u >= 1e-2) r = (*lnx - *lny) / d;
+  } else {
+    far |= u >= 1e-2;
+  }
+  return r;
+}
+
+// Ranocha's entropy-conservative, kinetic-energy-preserving two-point flux
+// along direction l between states given by (rho, v, p, beta = rho/p):
+//   f_rho = {{rho}}_ln {{v_l}},  f_v_d = f_rho {{v_d}} + {{p}} delta_dl,
+//   f_E = f_rho (1 / ((gamma - 1) {{beta}}_ln) + v_i . v_m / 2)
+//         + (p_i v_m,l + p_m v_i,l) / 2.
+// The node primitives sit in LDS rows Q[0] = rho, Q[1..DIM] = v,
+// Q[DIM+1] = p, Q[DIM+2] = beta, Q[DIM+3] = ln rho, Q[DIM+4] = ln beta; i is the
+// own node (its values also passed in registers), m the partner.
+template <int DIM, int l, bool EXACT, int W>
+__device__ __forceinline__ void ranocha_flux(double ri, const double (&vi)[DIM], double pi, double bi,
+                                             const double (*Q)[W], int i, int m, double gm1i, bool& far,
+                                             double (&F)[DIM + 2]) {
+  const double rm = Q[0][m], pm = Q[DIM + 1][m], bm = Q[DIM + 2][m];
+  double vm[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) vm[d] = Q[1 + d][m];
+  const double rho_ln = log_mean<EXACT>(ri, rm, &Q[DIM + 3][i], &Q[DIM + 3][m], far);
+  const double ib_ln = inv_log_mean<EXACT>(bi, bm, &Q[DIM + 4][i], &Q[DIM + 4][m], far);
+  double va[DIM];
+  double vv = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    va[d] = 0.5 * (vi[d] + vm[d]);
+    vv = fma(vi[d], vm[d], vv);
+  }
+  const double fr = rho_ln * va[l];
+  F[0] = fr;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) F[1 + d] = fr * va[d];
+  F[1 + l] += 0.5 * (pi + pm);
+  F[DIM + 1] = fma(fr, fma(ib_ln, gm1i, 0.5 * vv), 0.5 * fma(pi, vm[l], pm * vi[l]));
+}
+
+// One term of the split sum: s += D_im F#_l(U_i, U_m) for the k-th partner
+// m = i + k (mod n) of the lane's line along l.
+template <int DIM, int N, int l, bool EXACT, int W>
+__device__ __forceinline__ void split_term(int k, int tid, int il, int base, int st, double rho,
+                                           const double (&vel)[DIM], double p, double beta, const double (*Q)[W],
+                                           const double* sD, double gm1i, bool& far, double (&s)[DIM + 2]) {
+  constexpr int n = N + 1;
+  const int m = il + k < n ? il + k : il + k - n;
+  double F[DIM + 2];
+  ranocha_flux<DIM, l, EXACT>(rho, vel, p, beta, Q, tid, base + m * st, gm1i, far, F);
+  const double dim = sD[il * n + m];
+#pragma unroll
+  for (int v = 0; v < DIM + 2; ++v) s[v] = fma(dim, F[v], s[v]);
+}
+
+// Split-form volume sum of one lane, directions l..DIM-1:
+// acc -= 2 (2/h_l) sum_{m != i} D_im F#_l(U_i, U_m) over the lane's line along
+// l.  The partner index runs i+1, ..., i+N modulo n, so every lane makes the
+// same N flux evaluations per direction (the m = i term is added elsewhere).
+// The fast form is fully unrolled; the exact form keeps its partner loop
+// rolled (it only runs for lanes with widely separated partner states).
+template <int DIM, int N, int l, bool EXACT, int W>
+__device__ __forceinline__ void split_sweep(int tid, const int (&ii)[3], const int (&stride)[3], double rho,
+                                            const double (&vel)[DIM], double p, const double (*Q)[W],
+                                            const double* sD, const double (&g)[DIM], double gm1i, bool& far,
+                                            double (&acc)[DIM + 2]) {
+  if constexpr (l < DIM) {
+    constexpr int NV = DIM + 2;
+    const double beta = Q[DIM + 2][tid];
+    const int il = ii[l];
+    const int st = stride[l];
+    const int base = tid - il * st;
+    double s[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) s[v] = 0.0;
+    if constexpr (EXACT) {
+#pragma unroll 1
+      for (int k = 1; k <= N; ++k)
+        split_term<DIM, N, l, true>(k, tid, il, base, st, rho, vel, p, beta, Q, sD, gm1i, far, s);
+    } else {
+#pragma unroll
+      for (int k = 1; k <= N; ++k)
+        split_term<DIM, N, l, false>(k, tid, il, base, st, rho, vel, p, beta, Q, sD, gm1i, far, s);
+    }
+    const double c = -2.0 * g[l];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = fma(c, s[v], acc[v]);
+    split_sweep<DIM, N, l + 1, EXACT>(tid, ii, stride, rho, vel, p, Q, sD, g, gm1i, far, acc);
+  }
+}
+
 // register budget: four waves per SIMD; the reacting physics (eight
 // variables, mortar faces, 77,824-node workloads) takes three, which it needs
-// to keep its face state in registers
-template <class PHYS>
+// to keep its face state in registers, and so does the split form, whose
+// unrolled two-point fluxes would spill at four
+template <class PHYS, bool SPLIT>
 struct StageWaves {
-  static constexpr int value = PHYS::NV > 5 ? 3 : 4;
+  static constexpr int value = (PHYS::NV > 5 || SPLIT) ? 3 : 4;
 };
 
-template <int DIM, int N, class PHYS, typename T, bool MORTAR>
-__global__ void __launch_bounds__((Shape<DIM, N>::BS)) __attribute__((amdgpu_waves_per_eu(StageWaves<PHYS>::value)))
+template <int DIM, int N, class PHYS, typename T, bool MORTAR, bool SPLIT>
+__global__ void __launch_bounds__((Shape<DIM, N>::BS)) __attribute__((amdgpu_waves_per_eu(StageWaves<PHYS, SPLIT>::value)))
 k_stage(StageParams sp, MeshView mv, PhysConst pc) {
   using S = Shape<DIM, N>;
   constexpr int n = S::n, NP = S::NP, EPB = S::EPB, NV = PHYS::NV, MOM = PHYS::MOM;
@@ -59,15 +204,20 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
   constexpr bool UNIFORM_ELEM = (NP % 64) == 0;
   constexpr bool MASK_FACES = !F32 && !MORTAR;
 
-  __shared__ T sF[DIM][NV][EPB * NP];
-  __shared__ T sD[n * n];
-  __shared__ double sRef[F32 ? EPB : 1][DIM][NV];
+  // D in the sweep's precision: the split form sums in double
+  using DT = typename std::conditional<SPLIT, double, T>::type;
+  static_assert(!SPLIT || std::is_same<PHYS, EulerPhys<DIM>>::value, "split form: Euler physics");
+
+  __shared__ T sF[SPLIT ? 1 : DIM][SPLIT ? 1 : NV][SPLIT ? 1 : EPB * NP];
+  __shared__ double sQ[SPLIT ? DIM + 5 : 1][SPLIT ? EPB * NP : 1];  // rho, v, p, rho/p, their logs
+  __shared__ DT sD[n * n];
+  __shared__ double sRef[(F32 && !SPLIT) ? EPB : 1][DIM][NV];
 
   const int tid = threadIdx.x;
   // the lane's entry of D, stored to LDS only just before the first barrier
   // (no wait on this load ahead of the state loads)
   static_assert(n * n <= S::BS, "one D entry per lane");
-  const T dval = tid < n * n ? dmat_entry<T>(mv.K, tid) : T(0);
+  const DT dval = tid < n * n ? dmat_entry<DT>(mv.K, tid) : DT(0);
 
   const int E = mv.E;
   const int nEB = (E + EPB - 1) / EPB;
@@ -159,9 +309,20 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
 #pragma unroll
   for (int d = 0; d < DIM; ++d) vel[d] = u[MOM + d] * th.ri;
 
-  // ---- stage physical fluxes in LDS -------------------------------------
+  // ---- stage physical fluxes (split form: primitives) in LDS -------------
   if (tid < n * n) sD[tid] = dval;
-  if constexpr (F32) {
+  if constexpr (SPLIT) {
+    if (tid < S::NT) {
+      sQ[0][tid] = u[0];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) sQ[1 + d][tid] = vel[d];
+      sQ[DIM + 1][tid] = th.p;
+      const double beta = u[0] * frcp(th.p);
+      sQ[DIM + 2][tid] = beta;
+      sQ[DIM + 3][tid] = log(u[0]);
+      sQ[DIM + 4][tid] = log(beta);
+    }
+  } else if constexpr (F32) {
     if (tid < S::NT && node == 0) {
 #pragma unroll
       for (int l = 0; l < DIM; ++l) {
@@ -173,7 +334,7 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
     }
     __syncthreads();
   }
-  if (tid < S::NT) {
+  if (!SPLIT && tid < S::NT) {
 #pragma unroll
     for (int l = 0; l < DIM; ++l) {
       double F[NV];
@@ -191,7 +352,18 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
   double acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-  if (tid < S::NT) {
+  if constexpr (SPLIT) {
+    if (tid < S::NT) {
+      const double gm1i = 1.0 / (pc.gamma - 1.0);
+      bool far = false;
+      split_sweep<DIM, N, 0, false>(tid, ii, stride, u[0], vel, th.p, sQ, sD, g, gm1i, far, acc);
+      if (far) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+        split_sweep<DIM, N, 0, true>(tid, ii, stride, u[0], vel, th.p, sQ, sD, g, gm1i, far, acc);
+      }
+    }
+  } else if (tid < S::NT) {
 #pragma unroll
     for (int l = 0; l < DIM; ++l) {
       const int il = ii[l];
@@ -217,7 +389,7 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
     if (MASK_FACES && side[l] < 0) continue;  // masked lane: no face in direction l
     // own physical flux: the FP64 form reads it back from the volume stage
     double Fo[NV];
-    if constexpr (F32) {
+    if constexpr (F32 || SPLIT) {
       PHYS::flux(u, vel[l], th.p, l, Fo);
     } else {
 #pragma unroll
@@ -249,6 +421,12 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
     const double sc = (side[l] == 1 ? -g[l] : g[l]) * hwinv;
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = fma(sc, Dv[v], acc[v]);
+    if constexpr (SPLIT) {
+      // the split sum's m = i term, 2 D_ii F_l(U_i)
+      const double cd = -2.0 * g[l] * static_cast<double>(sD[ii[l] * (n + 1)]);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[v] = fma(cd, Fo[v], acc[v]);
+    }
   }
 
   // ---- output ----------------------------------------------------------------
@@ -335,25 +513,26 @@ k_mortar(const MortarRec* recs, const T* U, MeshView mv, PhysConst pc) {
 // ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
-template <int DIM, int N, class PHYS, typename T, bool MORTAR>
+template <int DIM, int N, class PHYS, typename T, bool MORTAR, bool SPLIT>
 static hipError_t go(const Ctx& c, const StageParams& sp, hipStream_t s) {
   using SH = Shape<DIM, N>;
   const int nEB = (c.E + SH::EPB - 1) / SH::EPB;
   const int nblk = nEB * c.B;
-  hipLaunchKernelGGL((k_stage<DIM, N, PHYS, T, MORTAR>), dim3(nblk), dim3(SH::BS), 0, s, sp, mesh_view(c), c.pc);
+  hipLaunchKernelGGL((k_stage<DIM, N, PHYS, T, MORTAR, SPLIT>), dim3(nblk), dim3(SH::BS), 0, s, sp, mesh_view(c),
+                     c.pc);
   return hipGetLastError();
 }
 
-template <int DIM, class PHYS, typename T, bool MORTAR>
+template <int DIM, class PHYS, typename T, bool MORTAR, bool SPLIT>
 static hipError_t go_n(const Ctx& c, const StageParams& sp, hipStream_t s) {
   switch (c.N) {
-    case 1: return go<DIM, 1, PHYS, T, MORTAR>(c, sp, s);
-    case 2: return go<DIM, 2, PHYS, T, MORTAR>(c, sp, s);
-    case 3: return go<DIM, 3, PHYS, T, MORTAR>(c, sp, s);
-    case 4: return go<DIM, 4, PHYS, T, MORTAR>(c, sp, s);
-    case 5: return go<DIM, 5, PHYS, T, MORTAR>(c, sp, s);
-    case 6: return go<DIM, 6, PHYS, T, MORTAR>(c, sp, s);
-    case 7: return go<DIM, 7, PHYS, T, MORTAR>(c, sp, s);
+    case 1: return go<DIM, 1, PHYS, T, MORTAR, SPLIT>(c, sp, s);
+    case 2: return go<DIM, 2, PHYS, T, MORTAR, SPLIT>(c, sp, s);
+    case 3: return go<DIM, 3, PHYS, T, MORTAR, SPLIT>(c, sp, s);
+    case 4: return go<DIM, 4, PHYS, T, MORTAR, SPLIT>(c, sp, s);
+    case 5: return go<DIM, 5, PHYS, T, MORTAR, SPLIT>(c, sp, s);
+    case 6: return go<DIM, 6, PHYS, T, MORTAR, SPLIT>(c, sp, s);
+    case 7: return go<DIM, 7, PHYS, T, MORTAR, SPLIT>(c, sp, s);
   }
   return hipErrorInvalidValue;
 }
@@ -361,11 +540,15 @@ static hipError_t go_n(const Ctx& c, const StageParams& sp, hipStream_t s) {
 template <typename T>
 static hipError_t stage_t(const Ctx& c, const StageParams& sp, hipStream_t s) {
   if (c.desc.physics == DG_REACTING_EULER) {
-    if (c.dim == 2 && c.N == 3 && c.mech.nspecies == 5) return go<2, 3, ReactPhys<2, 5>, T, true>(c, sp, s);
+    if (c.dim == 2 && c.N == 3 && c.mech.nspecies == 5) return go<2, 3, ReactPhys<2, 5>, T, true, false>(c, sp, s);
     return hipErrorInvalidValue;
   }
-  if (c.dim == 2) return go_n<2, EulerPhys<2>, T, true>(c, sp, s);
-  return go_n<3, EulerPhys<3>, T, false>(c, sp, s);
+  if (c.desc.volume == DG_VOLUME_SPLIT) {
+    if (c.dim == 2) return go_n<2, EulerPhys<2>, T, true, true>(c, sp, s);
+    return go_n<3, EulerPhys<3>, T, false, true>(c, sp, s);
+  }
+  if (c.dim == 2) return go_n<2, EulerPhys<2>, T, true, false>(c, sp, s);
+  return go_n<3, EulerPhys<3>, T, false, false>(c, sp, s);
 }
 
 hipError_t launch_stage(const Ctx& c, const StageParams& sp, hipStream_t s) {

@@ -15,6 +15,7 @@ from ._abi import check
 
 PHYSICS = {"euler": _abi.DG_EULER, "navier_stokes": _abi.DG_NAVIER_STOKES, "reacting": _abi.DG_REACTING_EULER}
 PRECISION = {"f64": _abi.DG_F64, "f32": _abi.DG_F32}
+VOLUME = {"standard": _abi.DG_VOLUME_STANDARD, "split": _abi.DG_VOLUME_SPLIT}
 
 
 def mechanism_struct(mech):
@@ -47,7 +48,7 @@ class Solver:
 
     def __init__(self, dim, degree, nel, lo, hi, physics="euler", precision="f64", batch=1,
                  patch_lo=None, patch_hi=None, gamma=1.4, mu=0.0, prandtl=0.72, mech=None,
-                 newton_max_iter=25, newton_tol=1e-13, device=0):
+                 newton_max_iter=25, newton_tol=1e-13, device=0, volume="standard"):
         self.lib = _abi.load()
         d = _abi.Desc()
         d.dim, d.degree = int(dim), int(degree)
@@ -66,9 +67,10 @@ class Solver:
         d.mech = ctypes.pointer(self._mech) if self._mech is not None else None
         d.newton_max_iter, d.newton_tol = int(newton_max_iter), float(newton_tol)
         d.device = int(device)
+        d.volume = VOLUME[volume]
         self.device = torch.device("cuda", int(device))
         self.dim, self.N, self.batch = int(dim), int(degree), int(batch)
-        self.physics, self.precision = physics, precision
+        self.physics, self.precision, self.volume = physics, precision, volume
         self.dtype = torch.float64 if precision == "f64" else torch.float32
         ctx = ctypes.c_void_p()
         check(self.lib.dg_create(ctypes.byref(d), ctypes.byref(ctx)), "dg_create")

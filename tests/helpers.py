@@ -7,12 +7,13 @@ import torch
 
 import dginputs as di
 from oracle.dgsem import Operator
+from oracle.split import SplitOperator
 from oracle.mesh import cartesian_mesh
 from oracle.physics import Euler, ReactingEuler
 
 
 def make_pair(dim, N, nel, lo, hi, physics="euler", precision="f64", batch=1, patch=None,
-              mu=0.0, prandtl=0.72, mech=None):
+              mu=0.0, prandtl=0.72, mech=None, volume="standard"):
     from paper_2605_26388_amd import Solver
     plo, phi = patch if patch else (None, None)
     mesh = cartesian_mesh(dim, N, nel, lo, hi, plo, phi)
@@ -23,9 +24,12 @@ def make_pair(dim, N, nel, lo, hi, physics="euler", precision="f64", batch=1, pa
         phys = Euler(dim)
         if physics == "navier_stokes":
             viscous = dict(mu=mu, prandtl=prandtl, gamma=1.4)
-    op = Operator(mesh, phys, viscous=viscous)
+    if volume == "split":
+        op = SplitOperator(mesh, phys)
+    else:
+        op = Operator(mesh, phys, viscous=viscous)
     s = Solver(dim, N, nel, lo, hi, physics=physics, precision=precision, batch=batch,
-               patch_lo=plo, patch_hi=phi, mu=mu, prandtl=prandtl, mech=mech)
+               patch_lo=plo, patch_hi=phi, mu=mu, prandtl=prandtl, mech=mech, volume=volume)
     assert s.E == mesh.E
     return op, s
 

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(_abi.LIB_PATH), reason="libdg
 
 
 def desc(dim=3, degree=3, nel=(4, 4, 4), physics=_abi.DG_EULER, precision=_abi.DG_F64, batch=1,
-         patch=None, gamma=1.4, mu=0.0, prandtl=0.72, mech=None):
+         patch=None, gamma=1.4, mu=0.0, prandtl=0.72, mech=None, volume=_abi.DG_VOLUME_STANDARD):
     d = _abi.Desc()
     d.dim, d.degree, d.physics, d.precision, d.batch = dim, degree, physics, precision, batch
     for l in range(3):
@@ -26,6 +26,7 @@ def desc(dim=3, degree=3, nel=(4, 4, 4), physics=_abi.DG_EULER, precision=_abi.D
     d.gamma, d.mu, d.prandtl = gamma, mu, prandtl
     d.mech = mech
     d.newton_max_iter, d.newton_tol, d.device = 25, 1e-13, 0
+    d.volume = volume
     return d
 
 
@@ -54,6 +55,8 @@ def create(d):
     (dict(dim=2, nel=(8, 8), patch=((0, 2), (8, 4))), _abi.DG_ERR_UNSUPPORTED, "period"),
     # just above the 32-bit state addressing limit: 119^3 elements x 64 nodes x 5 x 8 B > 4 GiB
     (dict(nel=(119, 119, 119)), _abi.DG_ERR_UNSUPPORTED, "4 GiB"),
+    (dict(volume=2), _abi.DG_ERR_ARG, "volume"),
+    (dict(volume=_abi.DG_VOLUME_SPLIT, physics=_abi.DG_NAVIER_STOKES), _abi.DG_ERR_UNSUPPORTED, "split"),
 ])
 def test_invalid_descriptors_rejected(kw, code, msg):
     rc, err = create(desc(**kw))
@@ -77,7 +80,10 @@ def test_null_arguments():
     assert lib.dg_create(None, None) == _abi.DG_ERR_ARG
 
 
-def test_valid_descriptor_passes_the_checks():
-    rc, err = create(desc())
+@pytest.mark.parametrize("kw", [dict(), dict(volume=_abi.DG_VOLUME_SPLIT),
+                                dict(dim=2, nel=(8, 8), patch=((2, 2), (4, 4)), volume=_abi.DG_VOLUME_SPLIT,
+                                     precision=_abi.DG_F32)])
+def test_valid_descriptor_passes_the_checks(kw):
+    rc, err = create(desc(**kw))
     # no device here: the only failure left is the device query itself
     assert rc in (_abi.DG_OK, _abi.DG_ERR_HIP), (rc, err)
