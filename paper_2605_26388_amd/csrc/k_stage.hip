@@ -52,16 +52,19 @@ __device__ __forceinline__ double wave_sound(const Thermo& t) {
 
 // Logarithmic mean {{x}}_ln = (x - y) / (ln x - ln y) of positive x, y and its
 // reciprocal.  With f = (x - y)/(x + y) and u = f^2, ln(x/y) = 2 atanh f =
-// 2 f P(u), P(u) = sum_k u^k / (2k + 1), hence {{x}}_ln = (x + y) / (2 P(u)):
-// no cancellation as x -> y, and the limit x at x = y comes out exactly.  For
-// u < 1e-2 (x/y within about 1.22) P summed through u^7 leaves a relative
-// truncation below u^8/17 < 6e-18.  The fast form uses the series for every
-// pair and raises `far` where u >= 1e-2; the exact form takes the closed
-// form there, with ln x and ln y computed once per node and read from LDS.
-// Branches inside the unrolled sweep would make it spill registers, so a
-// lane that raised `far` redoes its whole volume sum in the exact form (a
-// path smooth states never take).
-__device__ __forceinline__ double atanh_ratio_series(double u) {
+// 2 f P(u), P(u) = sum_k u^k / (2k + 1), hence {{x}}_ln = (x + y) / (2 P(u)) =
+// (x + y) Q(u) / 2 with Q = 1/P = 1 - u/3 - 4u^2/45 - 44u^3/945 - ... (the
+// coefficients of the reciprocal power series, exact rationals below): no
+// cancellation as x -> y, the limit x at x = y comes out exactly, and no
+// division.  For u < 1e-2 (x/y within about 1.22) the series through u^7
+// leave a relative truncation below 1e-18.  The fast form uses the series for
+// every pair and raises `far` where u >= 1e-2; the exact form takes the
+// closed form there, with ln x and ln y read from LDS.  Branches inside the
+// unrolled sweep would make it spill registers, so a lane that raised `far`
+// redoes its whole volume sum in the exact form (a path smooth states never
+// take; the logarithms are only computed when some lane of the block needs
+// them).
+__device__ __forceinline__ double atanh_ratio_series(double u) {  // P(u)
   double P = 1.0 / 15.0;
   P = fma(P, u, 1.0 / 13.0);
   P = fma(P, u, 1.0 / 11.0);
@@ -72,14 +75,29 @@ __device__ __forceinline__ double atanh_ratio_series(double u) {
   return fma(P, u, 1.0);
 }
 
+__device__ __forceinline__ double inv_atanh_ratio_series(double u) {  // Q(u) = 1 / P(u)
+  double Q = -25865068.0 / 1915538625.0;
+  Q = fma(Q, u, -10719068.0 / 638512875.0);
+  Q = fma(Q, u, -10196.0 / 467775.0);
+  Q = fma(Q, u, -428.0 / 14175.0);
+  Q = fma(Q, u, -44.0 / 945.0);
+  Q = fma(Q, u, -4.0 / 45.0);
+  Q = fma(Q, u, -1.0 / 3.0);
+  return fma(Q, u, 1.0);
+}
+
+// Both means take the halves hx = x/2, hy = y/2 (the block stages halved
+// rho and beta): (x - y)/(x + y) = (hx - hy)/(hx + hy), so
+//   {{x}}_ln = (hx + hy) Q(u),   1 / {{x}}_ln = P(u) / (hx + hy),
+// and the closed forms are 2 (hx - hy) / (ln x - ln y) and its reciprocal.
 template <bool EXACT>
-__device__ __forceinline__ double log_mean(double x, double y, const double* lnx, const double* lny, bool& far) {
-  const double s = x + y, d = x - y;
-  const double f = d * frcp(s);
+__device__ __forceinline__ double log_mean(double hx, double hy, const double* lnx, const double* lny, bool& far) {
+  const double hs = hx + hy, hd = hx - hy;
+  const double f = hd * frcp(hs);
   const double u = f * f;
-  double r = 0.5 * s * frcp(atanh_ratio_series(u));
+  double r = hs * inv_atanh_ratio_series(u);
   if constexpr (EXACT) {
-    if (u >= 1e-2) r = d / (*lnx - *lny);
+    if (u >= 1e-2) r = 2.0 * hd / (*lnx - *lny);
   } else {
     far |= u >= 1e-2;
   }
@@ -87,63 +105,73 @@ __device__ __forceinline__ double log_mean(double x, double y, const double* lnx
 }
 
 template <bool EXACT>
-__device__ __forceinline__ double inv_log_mean(double x, double y, const double* lnx, const double* lny, bool& far) {
-  const double s = x + y, d = x - y;
-  const double rs = frcp(s);
-  const double f = d * rs;
+__device__ __forceinline__ double inv_log_mean(double hx, double hy, const double* lnx, const double* lny, bool& far) {
+  const double hs = hx + hy, hd = hx - hy;
+  const double rs = frcp(hs);
+  const double f = hd * rs;
   const double u = f * f;
-  double r = 2.0 * atanh_ratio_series(u) * rs;
+  double r = atanh_ratio_series(u) * rs;
   if constexpr (EXACT) {
-    if (u >= 1e-2) r = (*lnx - *lny) / d;
+    if (u >= 1e-2) r = (*lnx - *lny) / (2.0 * hd);
   } else {
     far |= u >= 1e-2;
   }
   return r;
 }
+
+// Own-node values a lane keeps in registers for its two-point fluxes.
+template <int DIM>
+struct SplitNode {
+  double hr;        // rho / 2
+  double v[DIM];    // velocity
+  double hv[DIM];   // velocity / 2
+  double p, hp;     // pressure and its half
+  double hb;        // rho / (2 p)
+};
 
 // Ranocha's entropy-conservative, kinetic-energy-preserving two-point flux
-// along direction l between states given by (rho, v, p, beta = rho/p):
+// along direction l between node i (registers) and node m (LDS):
 //   f_rho = {{rho}}_ln {{v_l}},  f_v_d = f_rho {{v_d}} + {{p}} delta_dl,
 //   f_E = f_rho (1 / ((gamma - 1) {{beta}}_ln) + v_i . v_m / 2)
-//         + (p_i v_m,l + p_m v_i,l) / 2.
-// The node primitives sit in LDS rows Q[0] = rho, Q[1..DIM] = v,
-// Q[DIM+1] = p, Q[DIM+2] = beta, Q[DIM+3] = ln rho, Q[DIM+4] = ln beta; i is the
-// own node (its values also passed in registers), m the partner.
+//         + (p_i v_m,l + p_m v_i,l) / 2,   beta = rho / p.
+// With halved velocities in LDS the arithmetic means are single additions,
+// v_i . v_m / 2 = v_i . (v_m / 2) and (p_i v_m,l + p_m v_i,l)/2 =
+// p_i (v_m,l / 2) + p_m (v_i,l / 2).  LDS rows: Q[0] = rho/2, Q[1..DIM] =
+// v/2, Q[DIM+1] = p, Q[DIM+2] = beta/2, Q[DIM+3] = ln rho, Q[DIM+4] = ln beta
+// (the last two filled only when the exact form runs).
 template <int DIM, int l, bool EXACT, int W>
-__device__ __forceinline__ void ranocha_flux(double ri, const double (&vi)[DIM], double pi, double bi,
-                                             const double (*Q)[W], int i, int m, double gm1i, bool& far,
-                                             double (&F)[DIM + 2]) {
-  const double rm = Q[0][m], pm = Q[DIM + 1][m], bm = Q[DIM + 2][m];
-  double vm[DIM];
+__device__ __forceinline__ void ranocha_flux(const SplitNode<DIM>& a, const double (*Q)[W], int i, int m,
+                                             double gm1i, bool& far, double (&F)[DIM + 2]) {
+  const double hrm = Q[0][m], pm = Q[DIM + 1][m], hbm = Q[DIM + 2][m];
+  double hvm[DIM];
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) vm[d] = Q[1 + d][m];
-  const double rho_ln = log_mean<EXACT>(ri, rm, &Q[DIM + 3][i], &Q[DIM + 3][m], far);
-  const double ib_ln = inv_log_mean<EXACT>(bi, bm, &Q[DIM + 4][i], &Q[DIM + 4][m], far);
+  for (int d = 0; d < DIM; ++d) hvm[d] = Q[1 + d][m];
+  const double rho_ln = log_mean<EXACT>(a.hr, hrm, &Q[DIM + 3][i], &Q[DIM + 3][m], far);
+  const double ib_ln = inv_log_mean<EXACT>(a.hb, hbm, &Q[DIM + 4][i], &Q[DIM + 4][m], far);
   double va[DIM];
-  double vv = 0.0;
+  double hvv = a.v[0] * hvm[0];
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
-    va[d] = 0.5 * (vi[d] + vm[d]);
-    vv = fma(vi[d], vm[d], vv);
+    va[d] = a.hv[d] + hvm[d];
+    if (d > 0) hvv = fma(a.v[d], hvm[d], hvv);
   }
   const double fr = rho_ln * va[l];
   F[0] = fr;
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) F[1 + d] = fr * va[d];
-  F[1 + l] += 0.5 * (pi + pm);
-  F[DIM + 1] = fma(fr, fma(ib_ln, gm1i, 0.5 * vv), 0.5 * fma(pi, vm[l], pm * vi[l]));
+  for (int d = 0; d < DIM; ++d) F[1 + d] = d == l ? fma(fr, va[d], fma(0.5, pm, a.hp)) : fr * va[d];
+  F[DIM + 1] = fma(fr, fma(ib_ln, gm1i, hvv), fma(a.p, hvm[l], pm * a.hv[l]));
 }
 
 // One term of the split sum: s += D_im F#_l(U_i, U_m) for the k-th partner
 // m = i + k (mod n) of the lane's line along l.
 template <int DIM, int N, int l, bool EXACT, int W>
-__device__ __forceinline__ void split_term(int k, int tid, int il, int base, int st, double rho,
-                                           const double (&vel)[DIM], double p, double beta, const double (*Q)[W],
-                                           const double* sD, double gm1i, bool& far, double (&s)[DIM + 2]) {
+__device__ __forceinline__ void split_term(int k, int tid, int il, int base, int st, const SplitNode<DIM>& a,
+                                           const double (*Q)[W], const double* sD, double gm1i, bool& far,
+                                           double (&s)[DIM + 2]) {
   constexpr int n = N + 1;
   const int m = il + k < n ? il + k : il + k - n;
   double F[DIM + 2];
-  ranocha_flux<DIM, l, EXACT>(rho, vel, p, beta, Q, tid, base + m * st, gm1i, far, F);
+  ranocha_flux<DIM, l, EXACT>(a, Q, tid, base + m * st, gm1i, far, F);
   const double dim = sD[il * n + m];
 #pragma unroll
   for (int v = 0; v < DIM + 2; ++v) s[v] = fma(dim, F[v], s[v]);
@@ -156,13 +184,12 @@ __device__ __forceinline__ void split_term(int k, int tid, int il, int base, int
 // The fast form is fully unrolled; the exact form keeps its partner loop
 // rolled (it only runs for lanes with widely separated partner states).
 template <int DIM, int N, int l, bool EXACT, int W>
-__device__ __forceinline__ void split_sweep(int tid, const int (&ii)[3], const int (&stride)[3], double rho,
-                                            const double (&vel)[DIM], double p, const double (*Q)[W],
-                                            const double* sD, const double (&g)[DIM], double gm1i, bool& far,
+__device__ __forceinline__ void split_sweep(int tid, const int (&ii)[3], const int (&stride)[3],
+                                            const SplitNode<DIM>& a, const double (*Q)[W], const double* sD,
+                                            const double (&g)[DIM], double gm1i, bool& far,
                                             double (&acc)[DIM + 2]) {
   if constexpr (l < DIM) {
     constexpr int NV = DIM + 2;
-    const double beta = Q[DIM + 2][tid];
     const int il = ii[l];
     const int st = stride[l];
     const int base = tid - il * st;
@@ -172,16 +199,16 @@ __device__ __forceinline__ void split_sweep(int tid, const int (&ii)[3], const i
     if constexpr (EXACT) {
 #pragma unroll 1
       for (int k = 1; k <= N; ++k)
-        split_term<DIM, N, l, true>(k, tid, il, base, st, rho, vel, p, beta, Q, sD, gm1i, far, s);
+        split_term<DIM, N, l, true>(k, tid, il, base, st, a, Q, sD, gm1i, far, s);
     } else {
 #pragma unroll
       for (int k = 1; k <= N; ++k)
-        split_term<DIM, N, l, false>(k, tid, il, base, st, rho, vel, p, beta, Q, sD, gm1i, far, s);
+        split_term<DIM, N, l, false>(k, tid, il, base, st, a, Q, sD, gm1i, far, s);
     }
     const double c = -2.0 * g[l];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = fma(c, s[v], acc[v]);
-    split_sweep<DIM, N, l + 1, EXACT>(tid, ii, stride, rho, vel, p, Q, sD, g, gm1i, far, acc);
+    split_sweep<DIM, N, l + 1, EXACT>(tid, ii, stride, a, Q, sD, g, gm1i, far, acc);
   }
 }
 
@@ -210,6 +237,7 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
 
   __shared__ T sF[SPLIT ? 1 : DIM][SPLIT ? 1 : NV][SPLIT ? 1 : EPB * NP];
   __shared__ double sQ[SPLIT ? DIM + 5 : 1][SPLIT ? EPB * NP : 1];  // rho, v, p, rho/p, their logs
+  __shared__ int sFar;  // split form: some lane of the block needs the exact log means
   __shared__ DT sD[n * n];
   __shared__ double sRef[(F32 && !SPLIT) ? EPB : 1][DIM][NV];
 
@@ -272,6 +300,7 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
   // mortar form would spill registers).
   int side[DIM], nbe[DIM];
   double un[DIM][NV];
+  auto load_neighbours = [&]() {
 #pragma unroll
   for (int l = 0; l < DIM; ++l) {
     side[l] = (ii[l] == 0) ? 0 : ((ii[l] == N) ? 1 : -1);
@@ -289,6 +318,10 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
       for (int v = 0; v < NV; ++v) un[l][v] = 0.0;
     }
   }
+  };
+  // the split form loads them after its volume sweep instead: they would
+  // stay live in registers through the sweep's two-point fluxes
+  if constexpr (!SPLIT) load_neighbours();
   // stage input U0, fetched early as well
   const bool use_u0 = (sp.mode != 0) && (sp.a != 0.0);
   double u0[NV];
@@ -311,17 +344,25 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
 
   // ---- stage physical fluxes (split form: primitives) in LDS -------------
   if (tid < n * n) sD[tid] = dval;
+  SplitNode<DIM> own;
   if constexpr (SPLIT) {
-    if (tid < S::NT) {
-      sQ[0][tid] = u[0];
+    own.hr = 0.5 * u[0];
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) sQ[1 + d][tid] = vel[d];
-      sQ[DIM + 1][tid] = th.p;
-      const double beta = u[0] * frcp(th.p);
-      sQ[DIM + 2][tid] = beta;
-      sQ[DIM + 3][tid] = log(u[0]);
-      sQ[DIM + 4][tid] = log(beta);
+    for (int d = 0; d < DIM; ++d) {
+      own.v[d] = vel[d];
+      own.hv[d] = 0.5 * vel[d];
     }
+    own.p = th.p;
+    own.hp = 0.5 * th.p;
+    own.hb = 0.5 * (u[0] * frcp(th.p));
+    if (tid < S::NT) {
+      sQ[0][tid] = own.hr;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) sQ[1 + d][tid] = own.hv[d];
+      sQ[DIM + 1][tid] = own.p;
+      sQ[DIM + 2][tid] = own.hb;
+    }
+    if (tid == 0) sFar = 0;
   } else if constexpr (F32) {
     if (tid < S::NT && node == 0) {
 #pragma unroll
@@ -353,14 +394,21 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = 0.0;
   if constexpr (SPLIT) {
-    if (tid < S::NT) {
-      const double gm1i = 1.0 / (pc.gamma - 1.0);
-      bool far = false;
-      split_sweep<DIM, N, 0, false>(tid, ii, stride, u[0], vel, th.p, sQ, sD, g, gm1i, far, acc);
-      if (far) {
+    const double gm1i = 1.0 / (pc.gamma - 1.0);
+    bool far = false;
+    if (tid < S::NT) split_sweep<DIM, N, 0, false>(tid, ii, stride, own, sQ, sD, g, gm1i, far, acc);
+    if (far) sFar = 1;
+    __syncthreads();
+    if (sFar) {  // block-uniform: some pair is too far apart for the series
+      if (tid < S::NT) {
+        sQ[DIM + 3][tid] = log(u[0]);
+        sQ[DIM + 4][tid] = log(2.0 * own.hb);
+      }
+      __syncthreads();
+      if (far) {  // only the lanes that flagged a far pair redo their sum
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-        split_sweep<DIM, N, 0, true>(tid, ii, stride, u[0], vel, th.p, sQ, sD, g, gm1i, far, acc);
+        split_sweep<DIM, N, 0, true>(tid, ii, stride, own, sQ, sD, g, gm1i, far, acc);
       }
     }
   } else if (tid < S::NT) {
@@ -381,6 +429,8 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
       }
     }
   }
+
+  if constexpr (SPLIT) load_neighbours();
 
   // ---- surface lift (eq. surf_int) ----------------------------------------
   const double aown = wave_sound<PHYS, F32>(th);
