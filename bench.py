@@ -295,6 +295,49 @@ def bench_split(steps, warmup):
     return out
 
 
+def bench_ssprk54(steps, warmup):
+    """SSPRK54 steps (five fused stage launches, the fourth writing two
+    combinations) on the headline mesh, standard form and the paper's
+    production setting (split form, positivity floor rho >= 1e-6,
+    p >= 5e-7), FP64.  Reports the step time, the mean stage launch and the
+    cost per unit simulated time relative to SSP-RK3 at the same fraction of
+    each method's SSP step bound (SSP coefficients 1.508 and 1)."""
+    from paper_2605_26388_amd import Solver
+    p = di.PRESETS["euler3d"]
+    out = {}
+    for name, kw in (("standard", {}), ("split_floor", dict(volume="split", rho_floor=1e-6, p_floor=5e-7))):
+        s = Solver(3, p["N"], p["nel"], p["lo"], p["hi"], **kw)
+        X = s.node_coords().cpu().numpy()
+        U = torch.tensor(di.random_euler(X, p["lo"], p["hi"]))[None].to(s.device).contiguous()
+        dt = s.dt_cfl(U, p["cfl"])
+        t1, t2, t3, W = s.empty(), s.empty(), s.empty(), U.clone()
+        for k in range(warmup):
+            if k % 100 == 0:
+                W.copy_(U)
+            s.ssprk54_step(W, 1.508 * dt, t1, t2, t3)
+        stream = torch.cuda.current_stream()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        a.record(stream)
+        for _ in range(steps):
+            s.ssprk54_step(U, 1.508 * dt, t1, t2, t3)
+        b.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        gpu = a.elapsed_time(b) * 1e-3
+        st = s.status()
+        assert st["nonphysical"] == 0, st
+        dof = s.E * s.Np * s.nv
+        out[name] = {"ms_per_step": wall / steps * 1e3, "stage_us": gpu / (5 * steps) * 1e6,
+                     "dof_updates_per_s": 5 * dof * steps / wall, "floored": st["floored"]}
+        s.close()
+    out["cost_per_simulated_time_vs_ssprk3"] = (5 / 1.508) / 3
+    out["workload"] = ("euler3d: 3-D Euler 32^3, N=3, SSPRK54 at 1.508 x the SSP-RK3 step (CFL 0.5), FP64; "
+                       "split_floor: split form with the positivity floor")
+    return out
+
+
 def bench_adjoint(steps):
     """Adjoint workload (16^3, N=3, batch 8) in FP32: forward SSP-RK3 step vs
     its reverse sweep with stored stage states."""
@@ -330,7 +373,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--only", choices=["f64", "f32"], default=None,
                     help="time one form only (profiling runs)")
-    ap.add_argument("--side", choices=["adjoint", "navier_stokes", "navier_stokes_L", "reacting", "split"],
+    ap.add_argument("--side", choices=["adjoint", "navier_stokes", "navier_stokes_L", "reacting", "split", "ssprk54"],
                     default=None,
                     help="instead: run one side workload alone and print its JSON (profiling runs)")
     ap.add_argument("--calib-copy", type=int, default=0,
@@ -357,7 +400,8 @@ def main():
               "navier_stokes": lambda: bench_navier_stokes(reps),
               "navier_stokes_L": lambda: bench_navier_stokes(reps, nel=(32, 32, 32)),
               "reacting": lambda: bench_reacting(reps),
-              "split": lambda: bench_split(args.steps, args.warmup)}[args.side]
+              "split": lambda: bench_split(args.steps, args.warmup),
+              "ssprk54": lambda: bench_ssprk54(args.steps, args.warmup // 2)}[args.side]
         print(json.dumps({args.side: fn()}), flush=True)
         return
 
@@ -424,6 +468,8 @@ def main():
         out["reacting"] = bench_reacting(max(5, args.steps // 10))
         log("split-form workload ...")
         out["split"] = bench_split(args.steps, args.warmup)
+        log("SSPRK54 workload ...")
+        out["ssprk54"] = bench_ssprk54(args.steps, args.warmup // 2)
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(dict(p, N=3))

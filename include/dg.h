@@ -116,6 +116,13 @@ typedef struct dg_desc {
   double newton_tol;       /* stop when max |dY| <= tol * rho, default 1e-13 */
   int32_t device;          /* HIP device ordinal the context lives on */
   int32_t volume;          /* dg_volume; 0 (standard) when zero-initialised */
+  /* Per-stage positivity floor (the paper's rho >= rho_min, p >= p_min after
+   * every stage): applied node by node to the stage output of dg_rk_stage and
+   * to the first output of dg_rk_stage_dual, never to dg_rhs.  rho is
+   * clipped to rho_floor with the momentum unchanged, then E is raised to
+   * p_floor/(gamma-1) + |m|^2/(2 rho) where it lies below.  0 for both turns
+   * it off; Euler and Navier-Stokes physics only. */
+  double rho_floor, p_floor;
 } dg_desc;
 
 /* Sticky device-side counters (dg_status_read). */
@@ -126,6 +133,7 @@ typedef struct dg_counters {
   int32_t newton_iters_max;  /* largest iteration count of any node */
   int64_t first_bad;         /* flat (b*E + e)*Np + node of the first
                                 non-physical node seen, -1 if none */
+  int32_t floored;           /* stage outputs changed by the positivity floor */
 } dg_counters;
 
 typedef struct dg_ctx dg_ctx;
@@ -158,6 +166,26 @@ int dg_rhs(dg_ctx* ctx, const void* U, void* dUdt, void* stream);
  * Uout == U0 is allowed.  U0 is not read when a == 0. */
 int dg_rk_stage(dg_ctx* ctx, const void* U0, const void* Uk, void* Uout,
                 double a, double b, double c_dt, void* stream);
+
+/* Two Shu-Osher combinations of one evaluation of L(U_k), for methods whose
+ * later stage reuses L of an earlier one (SSP-RK appendix; SSPRK54 needs
+ * L(U^(3)) in stages 4 and 5):
+ *   Uout = a U0 + b Uk + c_dt L(Uk)    (positivity floor applied, if set)
+ *   Wout = a2 V + b2 Uk + c2_dt L(Uk)  (no floor: a partial sum, not a stage)
+ * Same layout and stream semantics as dg_rk_stage.  U0 may equal Uout and V
+ * may equal Wout (in place); Uk must not alias either output, the outputs
+ * must not overlap each other, and U0 (V) is not read when a (a2) is 0. */
+int dg_rk_stage_dual(dg_ctx* ctx, const void* U0, const void* Uk, void* Uout, double a, double b, double c_dt,
+                     const void* V, void* Wout, double a2, double b2, double c2_dt, void* stream);
+
+/* One step of the five-stage, fourth-order SSP Runge-Kutta method of Spiteri
+ * and Ruuth (SSP coefficient 1.508; SSP-RK appendix, Shu-Osher form with the
+ * method's published coefficients), in place on U: U <- U^(5).  Five fused
+ * stage launches; the fourth is the dual form (it also forms the part of
+ * U^(5) that needs L(U^(3))).  t1, t2, t3 are caller-owned scratch states of
+ * the state's size, distinct from U and from each other; afterwards t3 holds
+ * U^(4).  The positivity floor, if set, applies to U^(1), ..., U^(5). */
+int dg_ssprk54_step(dg_ctx* ctx, void* U, double dt, void* t1, void* t2, void* t3, void* stream);
 
 /* Chemistry source (reacting Euler only; arithmetic in double always).
  * mode 0: out += S(U), S from eqs. src_reaction_rate / src_omega (species

@@ -20,7 +20,8 @@ DG_F64, DG_F32 = range(2)
 DG_VOLUME_STANDARD, DG_VOLUME_SPLIT = range(2)
 
 EXPORTS = (
-    "dg_create", "dg_destroy", "dg_sizes", "dg_node_coords", "dg_rhs", "dg_rk_stage",
+    "dg_create", "dg_destroy", "dg_sizes", "dg_node_coords", "dg_rhs", "dg_rk_stage", "dg_rk_stage_dual",
+    "dg_ssprk54_step",
     "dg_source_chem", "dg_rhs_adjoint", "dg_rk_stage_adjoint", "dg_dt_cfl", "dg_integrals",
     "dg_status_read", "dg_strerror", "dg_last_error",
 )
@@ -52,13 +53,14 @@ class Desc(ctypes.Structure):
         ("mech", POINTER(Mechanism)),
         ("newton_max_iter", c_int32), ("newton_tol", c_double), ("device", c_int32),
         ("volume", c_int32),
+        ("rho_floor", c_double), ("p_floor", c_double),
     ]
 
 
 class Counters(ctypes.Structure):
     _fields_ = [
         ("nonphysical", c_int32), ("newton_unconverged", c_int32), ("species_clips", c_int32),
-        ("newton_iters_max", c_int32), ("first_bad", c_int64),
+        ("newton_iters_max", c_int32), ("first_bad", c_int64), ("floored", c_int32),
     ]
 
 
@@ -81,6 +83,9 @@ def load():
         "dg_node_coords": (c_int32, [P, P, P]),
         "dg_rhs": (c_int32, [P, P, P, P]),
         "dg_rk_stage": (c_int32, [P, P, P, P, c_double, c_double, c_double, P]),
+        "dg_rk_stage_dual": (c_int32, [P, P, P, P, c_double, c_double, c_double, P, P, c_double, c_double,
+                                       c_double, P]),
+        "dg_ssprk54_step": (c_int32, [P, P, c_double, P, P, P, P]),
         "dg_source_chem": (c_int32, [P, P, P, c_double, c_int32, P]),
         "dg_rhs_adjoint": (c_int32, [P, P, P, P, P]),
         "dg_rk_stage_adjoint": (c_int32, [P, P, P, P, P, c_double, c_double, c_double, c_int32, P]),

@@ -457,6 +457,10 @@ int dg_create(const dg_desc* desc, dg_ctx** out) {
       break;
     default: return fail(DG_ERR_ARG, "unknown physics");
   }
+  if (!(d.rho_floor >= 0.0) || !(d.p_floor >= 0.0) || !std::isfinite(d.rho_floor) || !std::isfinite(d.p_floor))
+    return fail(DG_ERR_ARG, "rho_floor and p_floor must be finite and >= 0");
+  if ((d.rho_floor > 0.0 || d.p_floor > 0.0) && d.physics == DG_REACTING_EULER)
+    return fail(DG_ERR_UNSUPPORTED, "positivity floor: Euler and Navier-Stokes physics only");
   if (d.volume != DG_VOLUME_STANDARD && d.volume != DG_VOLUME_SPLIT)
     return fail(DG_ERR_ARG, "volume must be DG_VOLUME_STANDARD or DG_VOLUME_SPLIT");
   if (d.volume == DG_VOLUME_SPLIT && d.physics != DG_EULER)
@@ -583,7 +587,8 @@ int dg_node_coords(const dg_ctx* ctx, double* xyz, void* stream) {
 }
 
 static int run_stage(dg_ctx* ctx, const void* U0, const void* Uk, void* out, double a, double b, double cdt,
-                     int mode, void* stream, const char* who) {
+                     int mode, void* stream, const char* who, const void* V = nullptr, void* out2 = nullptr,
+                     double a2 = 0.0, double b2 = 0.0, double c2 = 0.0) {
   Ctx& c = ctx->c;
   const size_t bytes = state_bytes(c);
   if (overlaps(Uk, out, bytes)) return fail(DG_ERR_ARG, std::string(who) + ": output aliases the evaluated state");
@@ -597,6 +602,15 @@ static int run_stage(dg_ctx* ctx, const void* U0, const void* Uk, void* out, dou
   sp.b = b;
   sp.c = cdt;
   sp.mode = mode;
+  sp.V = V;
+  sp.out2 = out2;
+  sp.a2 = a2;
+  sp.b2 = b2;
+  sp.c2 = c2;
+  if (mode != 0) {
+    sp.rho_min = c.desc.rho_floor;
+    sp.p_min = c.desc.p_floor;
+  }
   hipError_t e;
   if (c.desc.physics == DG_NAVIER_STOKES) {
     e = launch_ns(c, sp, s);
@@ -618,6 +632,57 @@ int dg_rk_stage(dg_ctx* ctx, const void* U0, const void* Uk, void* Uout, double 
   if (a != 0.0 && U0 != Uout && overlaps(U0, Uout, state_bytes(ctx->c)))
     return fail(DG_ERR_ARG, "dg_rk_stage: Uout partially overlaps U0");
   return run_stage(ctx, U0, Uk, Uout, a, b, c_dt, 1, stream, "dg_rk_stage");
+}
+
+int dg_rk_stage_dual(dg_ctx* ctx, const void* U0, const void* Uk, void* Uout, double a, double b, double c_dt,
+                     const void* V, void* Wout, double a2, double b2, double c2_dt, void* stream) {
+  if (!ctx || !Uk || !Uout || !Wout || (a != 0.0 && !U0) || (a2 != 0.0 && !V))
+    return fail(DG_ERR_ARG, "dg_rk_stage_dual: null argument");
+  const size_t bytes = state_bytes(ctx->c);
+  if (a != 0.0 && U0 != Uout && overlaps(U0, Uout, bytes))
+    return fail(DG_ERR_ARG, "dg_rk_stage_dual: Uout partially overlaps U0");
+  if (a2 != 0.0 && V != Wout && overlaps(V, Wout, bytes))
+    return fail(DG_ERR_ARG, "dg_rk_stage_dual: Wout partially overlaps V");
+  if (overlaps(Uk, Wout, bytes)) return fail(DG_ERR_ARG, "dg_rk_stage_dual: Wout aliases the evaluated state");
+  if (overlaps(Uout, Wout, bytes)) return fail(DG_ERR_ARG, "dg_rk_stage_dual: the two outputs overlap");
+  // a stage output must not be read as the other combination's input either
+  if (a2 != 0.0 && overlaps(V, Uout, bytes)) return fail(DG_ERR_ARG, "dg_rk_stage_dual: V aliases Uout");
+  if (a != 0.0 && overlaps(U0, Wout, bytes)) return fail(DG_ERR_ARG, "dg_rk_stage_dual: U0 aliases Wout");
+  return run_stage(ctx, U0, Uk, Uout, a, b, c_dt, 2, stream, "dg_rk_stage_dual", V, Wout, a2, b2, c2_dt);
+}
+
+// Shu-Osher coefficients of SSPRK(5,4) (Spiteri and Ruuth), nonzero entries:
+// U^(i) = sum_k alpha_ik U^(k) + dt beta_ik L(U^(k)).
+namespace {
+constexpr double A20 = 0.444370493651235, A21 = 0.555629506348765;
+constexpr double A30 = 0.620101851488403, A32 = 0.379898148511597;
+constexpr double A40 = 0.178079954393132, A43 = 0.821920045606868;
+constexpr double A52 = 0.517231671970585, A53 = 0.096059710526147, A54 = 0.386708617503269;
+constexpr double B10 = 0.391752226571890, B21 = 0.368410593050371, B32 = 0.251891774271694;
+constexpr double B43 = 0.544974750228521, B53 = 0.063692468666290, B54 = 0.226007483236906;
+}  // namespace
+
+int dg_ssprk54_step(dg_ctx* ctx, void* U, double dt, void* t1, void* t2, void* t3, void* stream) {
+  if (!ctx || !U || !t1 || !t2 || !t3) return fail(DG_ERR_ARG, "dg_ssprk54_step: null argument");
+  const size_t bytes = state_bytes(ctx->c);
+  const void* bufs[4] = {U, t1, t2, t3};
+  for (int i = 0; i < 4; ++i)
+    for (int j = i + 1; j < 4; ++j)
+      if (overlaps(bufs[i], bufs[j], bytes)) return fail(DG_ERR_ARG, "dg_ssprk54_step: U, t1, t2, t3 must not overlap");
+  int rc;
+  // U^(1) = U + dt b10 L(U)                                   -> t1
+  if ((rc = run_stage(ctx, nullptr, U, t1, 0.0, 1.0, B10 * dt, 1, stream, "dg_ssprk54_step")) != DG_OK) return rc;
+  // U^(2) = a20 U + a21 U^(1) + dt b21 L(U^(1))                -> t2
+  if ((rc = run_stage(ctx, U, t1, t2, A20, A21, B21 * dt, 1, stream, "dg_ssprk54_step")) != DG_OK) return rc;
+  // U^(3) = a30 U + a32 U^(2) + dt b32 L(U^(2))                -> t1
+  if ((rc = run_stage(ctx, U, t2, t1, A30, A32, B32 * dt, 1, stream, "dg_ssprk54_step")) != DG_OK) return rc;
+  // U^(4) = a40 U + a43 U^(3) + dt b43 L(U^(3))                -> t3
+  // W     = a52 U^(2) + a53 U^(3) + dt b53 L(U^(3))            -> t2 (in place)
+  if ((rc = run_stage(ctx, U, t1, t3, A40, A43, B43 * dt, 2, stream, "dg_ssprk54_step", t2, t2, A52, A53,
+                      B53 * dt)) != DG_OK)
+    return rc;
+  // U^(5) = W + a54 U^(4) + dt b54 L(U^(4))                    -> U
+  return run_stage(ctx, t2, t3, U, 1.0, A54, B54 * dt, 1, stream, "dg_ssprk54_step");
 }
 
 int dg_source_chem(dg_ctx* ctx, const void* U, void* out, double h, int32_t mode, void* stream) {
@@ -720,6 +785,7 @@ int dg_status_read(dg_ctx* ctx, dg_counters* out, int32_t reset, void* stream) {
   out->species_clips = cnt[CNT_CLIPS];
   out->newton_iters_max = cnt[CNT_ITERS];
   out->first_bad = fb == ~0ull ? -1 : (int64_t)fb;
+  out->floored = cnt[CNT_FLOORED];
   return DG_OK;
 }
 

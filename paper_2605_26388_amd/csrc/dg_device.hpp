@@ -107,6 +107,31 @@ __device__ __forceinline__ double fsqrt(double x) {
   return fma(d, h, g);
 }
 
+// Positivity floor of an ideal-gas stage output r = (rho, m, E): rho is
+// clipped to rho_min with the momentum kept, then E is raised to
+// p_min/(gamma-1) + |m|^2/(2 rho) where it lies below, i.e. to pressure p_min.
+// Returns whether it changed anything.  Nodes it acts on are counted per wave
+// (one atomic per wave) in counters[CNT_FLOORED].
+template <int NV>
+__device__ __forceinline__ void positivity_floor(double (&r)[NV], double rho_min, double p_min, double gm1i,
+                                                 int* counters) {
+  bool acted = false;
+  if (r[0] < rho_min) {
+    r[0] = rho_min;
+    acted = true;
+  }
+  double m2 = 0.0;
+#pragma unroll
+  for (int d = 1; d < NV - 1; ++d) m2 = fma(r[d], r[d], m2);
+  const double emin = fma(0.5 * m2, frcp(r[0]), p_min * gm1i);
+  if (r[NV - 1] < emin) {
+    r[NV - 1] = emin;
+    acted = true;
+  }
+  const unsigned long long mask = __ballot(acted);
+  if (acted && (int)__lane_id() == __ffsll(mask) - 1) atomicAdd(&counters[CNT_FLOORED], (int)__popcll(mask));
+}
+
 // ---------------------------------------------------------------------------
 // Pointwise physics.  Thermo holds what a flux or a wave speed needs beyond U:
 // 1/rho, the pressure and the factor k with a^2 = k p / rho.

@@ -14,7 +14,7 @@ namespace dg {
 
 constexpr int MAXN1 = 8;  // highest supported N + 1
 
-enum CounterIdx { CNT_NONPHYSICAL = 0, CNT_NEWTON = 1, CNT_CLIPS = 2, CNT_ITERS = 3, CNT_N = 4 };
+enum CounterIdx { CNT_NONPHYSICAL = 0, CNT_NEWTON = 1, CNT_CLIPS = 2, CNT_ITERS = 3, CNT_FLOORED = 4, CNT_N = 5 };
 
 // Reference-element and mortar constants, resident in device memory.
 struct RefConsts {
@@ -62,7 +62,13 @@ struct StageParams {
   const void* Uk;
   void* out;
   double a, b, c;
-  int mode;  // 0: out = L(Uk);  1: out = a U0 + b Uk + c L(Uk)
+  int mode;  // 0: out = L(Uk);  1: out = a U0 + b Uk + c L(Uk);  2: also out2
+  // mode 2: out2 = a2 V + b2 Uk + c2 L(Uk), without the floor
+  const void* V = nullptr;
+  void* out2 = nullptr;
+  double a2 = 0.0, b2 = 0.0, c2 = 0.0;
+  // positivity floor on out (modes 1 and 2); off when both are 0
+  double rho_min = 0.0, p_min = 0.0;
 };
 
 struct Ctx {

@@ -287,14 +287,28 @@ k_ns(StageParams sp, MeshView mv, PhysConst pc, T* face) {
     }
     if (active) {
       T* outb = static_cast<T*>(sp.out) + (size_t)b * NV * plane;
+      double r[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        double r = acc[v];
+        r[v] = acc[v];
         if (sp.mode != 0) {
-          r = fma(sp.c, acc[v], sp.b * u[v]);
-          if (use_u0) r = fma(sp.a, u0[v], r);
+          r[v] = fma(sp.c, acc[v], sp.b * u[v]);
+          if (use_u0) r[v] = fma(sp.a, u0[v], r[v]);
         }
-        Buf<T>::store(make_rsrc(outb + v * plane, pbytes), off, r);
+      }
+      if (sp.mode != 0 && (sp.rho_min > 0.0 || sp.p_min > 0.0))
+        positivity_floor(r, sp.rho_min, sp.p_min, 1.0 / gm1, mv.counters);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Buf<T>::store(make_rsrc(outb + v * plane, pbytes), off, r[v]);
+      if (sp.mode == 2) {  // second combination of the same L(Uk), no floor
+        T* out2 = static_cast<T*>(sp.out2) + (size_t)b * NV * plane;
+        const T* Vb = static_cast<const T*>(sp.a2 != 0.0 ? sp.V : sp.Uk) + (size_t)b * NV * plane;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          double w = fma(sp.c2, acc[v], sp.b2 * u[v]);
+          if (sp.a2 != 0.0) w = fma(sp.a2, Buf<T>::load(make_rsrc(Vb + v * plane, pbytes), off), w);
+          Buf<T>::store(make_rsrc(out2 + v * plane, pbytes), off, w);
+        }
       }
     }
   }

@@ -13,7 +13,8 @@
 //      atomics) and evaluate the Rusanov flux with the element on the -xi_l
 //      side as left state, so both elements of a face get the same bits; 2:1
 //      mortar faces take the flux from the mortar kernel's rows instead;
-//   4. write dU/dt, or the stage a U0 + b U_k + c dU/dt.
+//   4. write dU/dt, or the stage a U0 + b U_k + c dU/dt (with the positivity
+//      floor, if set), and in the dual form also a2 V + b2 U_k + c2 dU/dt.
 //
 // Split form (eq. vol_split): instead of fluxes the block stages primitives
 // (rho, v, p, rho/p and the logarithms of rho and rho/p) in LDS, and each lane sums 2 D_im F#_l(U_i, U_m) over
@@ -486,11 +487,28 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) Buf<T>::store(ro, off, acc[v], v * pstride);
     } else {
+      double r[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        double r = fma(sp.c, acc[v], sp.b * u[v]);
-        if (use_u0) r = fma(sp.a, u0[v], r);
-        Buf<T>::store(ro, off, r, v * pstride);
+        r[v] = fma(sp.c, acc[v], sp.b * u[v]);
+        if (use_u0) r[v] = fma(sp.a, u0[v], r[v]);
+      }
+      if constexpr (std::is_same<PHYS, EulerPhys<DIM>>::value) {
+        if (sp.rho_min > 0.0 || sp.p_min > 0.0)
+          positivity_floor(r, sp.rho_min, sp.p_min, 1.0 / (pc.gamma - 1.0), mv.counters);
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Buf<T>::store(ro, off, r[v], v * pstride);
+      if (sp.mode == 2) {  // second combination of the same L(Uk), no floor
+        const rsrc_t r2 = make_rsrc(static_cast<T*>(sp.out2) + (size_t)b * NV * plane, abytes);
+        const bool use_v = sp.a2 != 0.0;
+        const rsrc_t rv = make_rsrc(static_cast<const T*>(use_v ? sp.V : sp.Uk) + (size_t)b * NV * plane, abytes);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          double w = fma(sp.c2, acc[v], sp.b2 * u[v]);
+          if (use_v) w = fma(sp.a2, Buf<T>::load(rv, off, v * pstride), w);
+          Buf<T>::store(r2, off, w, v * pstride);
+        }
       }
     }
   }

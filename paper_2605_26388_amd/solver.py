@@ -48,7 +48,7 @@ class Solver:
 
     def __init__(self, dim, degree, nel, lo, hi, physics="euler", precision="f64", batch=1,
                  patch_lo=None, patch_hi=None, gamma=1.4, mu=0.0, prandtl=0.72, mech=None,
-                 newton_max_iter=25, newton_tol=1e-13, device=0, volume="standard"):
+                 newton_max_iter=25, newton_tol=1e-13, device=0, volume="standard", rho_floor=0.0, p_floor=0.0):
         self.lib = _abi.load()
         d = _abi.Desc()
         d.dim, d.degree = int(dim), int(degree)
@@ -68,6 +68,7 @@ class Solver:
         d.newton_max_iter, d.newton_tol = int(newton_max_iter), float(newton_tol)
         d.device = int(device)
         d.volume = VOLUME[volume]
+        d.rho_floor, d.p_floor = float(rho_floor), float(p_floor)
         self.device = torch.device("cuda", int(device))
         self.dim, self.N, self.batch = int(dim), int(degree), int(batch)
         self.physics, self.precision, self.volume = physics, precision, volume
@@ -123,6 +124,25 @@ class Solver:
               "dg_rk_stage")
         return out
 
+    def rk_stage_dual(self, U0, Uk, out, a, b, c_dt, V, out2, a2, b2, c2_dt):
+        check(self.lib.dg_rk_stage_dual(self._ctx, self._ptr(U0, "U0") if a != 0.0 else None, self._ptr(Uk, "Uk"),
+                                        self._ptr(out, "Uout"), float(a), float(b), float(c_dt),
+                                        self._ptr(V, "V") if a2 != 0.0 else None, self._ptr(out2, "Wout"),
+                                        float(a2), float(b2), float(c2_dt), _stream(self.device)),
+              "dg_rk_stage_dual")
+        return out, out2
+
+    def ssprk54_step(self, U, dt, tmp1=None, tmp2=None, tmp3=None):
+        """One SSPRK54 step in place on U (three scratch states; tmp3 holds
+        U^(4) afterwards)."""
+        t1 = self.empty() if tmp1 is None else tmp1
+        t2 = self.empty() if tmp2 is None else tmp2
+        t3 = self.empty() if tmp3 is None else tmp3
+        check(self.lib.dg_ssprk54_step(self._ctx, self._ptr(U, "U"), float(dt), self._ptr(t1, "t1"),
+                                       self._ptr(t2, "t2"), self._ptr(t3, "t3"), _stream(self.device)),
+              "dg_ssprk54_step")
+        return U
+
     def source_chem(self, U, out, h, mode):
         check(self.lib.dg_source_chem(self._ctx, self._ptr(U, "U"), self._ptr(out, "out"), float(h), int(mode),
                                       _stream(self.device)), "dg_source_chem")
@@ -169,7 +189,8 @@ class Solver:
         check(self.lib.dg_status_read(self._ctx, ctypes.byref(c), int(bool(reset)), _stream(self.device)),
               "dg_status_read")
         return dict(nonphysical=c.nonphysical, newton_unconverged=c.newton_unconverged,
-                    species_clips=c.species_clips, newton_iters_max=c.newton_iters_max, first_bad=c.first_bad)
+                    species_clips=c.species_clips, newton_iters_max=c.newton_iters_max, first_bad=c.first_bad,
+                    floored=c.floored)
 
     # -- composite drivers (sequences of library calls) ------------------------
     def ssprk3_step(self, U, dt, tmp1=None, tmp2=None):

@@ -53,6 +53,7 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu\n", offsetof(dg_desc, mech), offsetof(dg_desc, gamma),
          offsetof(dg_desc, newton_tol), offsetof(dg_desc, device), offsetof(dg_desc, patch_hi),
          offsetof(dg_desc, volume));
+  printf("%zu %zu %zu\n", offsetof(dg_desc, rho_floor), offsetof(dg_desc, p_floor), offsetof(dg_counters, floored));
   printf("%zu %zu %zu\n", offsetof(dg_mechanism, nu_f), offsetof(dg_mechanism, eff),
          offsetof(dg_mechanism, kappa_r));
   printf("%zu\n", offsetof(dg_counters, first_bad));
@@ -69,7 +70,7 @@ int main(void) {
     M, D, C = _abi.Mechanism, _abi.Desc, _abi.Counters
     expect = [ctypes.sizeof(M), ctypes.sizeof(D), ctypes.sizeof(C),
               D.mech.offset, D.gamma.offset, D.newton_tol.offset, D.device.offset, D.patch_hi.offset,
-              D.volume.offset, M.nu_f.offset, M.eff.offset, M.kappa_r.offset, C.first_bad.offset]
+              D.volume.offset, D.rho_floor.offset, D.p_floor.offset, C.floored.offset, M.nu_f.offset, M.eff.offset, M.kappa_r.offset, C.first_bad.offset]
     assert vals == expect
 
 

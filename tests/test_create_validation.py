@@ -14,7 +14,8 @@ pytestmark = pytest.mark.skipif(not os.path.exists(_abi.LIB_PATH), reason="libdg
 
 
 def desc(dim=3, degree=3, nel=(4, 4, 4), physics=_abi.DG_EULER, precision=_abi.DG_F64, batch=1,
-         patch=None, gamma=1.4, mu=0.0, prandtl=0.72, mech=None, volume=_abi.DG_VOLUME_STANDARD):
+         patch=None, gamma=1.4, mu=0.0, prandtl=0.72, mech=None, volume=_abi.DG_VOLUME_STANDARD,
+         rho_floor=0.0, p_floor=0.0):
     d = _abi.Desc()
     d.dim, d.degree, d.physics, d.precision, d.batch = dim, degree, physics, precision, batch
     for l in range(3):
@@ -24,9 +25,15 @@ def desc(dim=3, degree=3, nel=(4, 4, 4), physics=_abi.DG_EULER, precision=_abi.D
         for l in range(2):
             d.patch_lo[l], d.patch_hi[l] = patch[0][l], patch[1][l]
     d.gamma, d.mu, d.prandtl = gamma, mu, prandtl
+    if mech == "air5":
+        import dginputs as di
+        from paper_2605_26388_amd.solver import mechanism_struct
+        d._mech_keep = mechanism_struct(di.air5_mechanism(di.PRESETS["air5_2d"]["mech_seed"]))
+        mech = ctypes.pointer(d._mech_keep)
     d.mech = mech
     d.newton_max_iter, d.newton_tol, d.device = 25, 1e-13, 0
     d.volume = volume
+    d.rho_floor, d.p_floor = rho_floor, p_floor
     return d
 
 
@@ -57,6 +64,11 @@ def create(d):
     (dict(nel=(119, 119, 119)), _abi.DG_ERR_UNSUPPORTED, "4 GiB"),
     (dict(volume=2), _abi.DG_ERR_ARG, "volume"),
     (dict(volume=_abi.DG_VOLUME_SPLIT, physics=_abi.DG_NAVIER_STOKES), _abi.DG_ERR_UNSUPPORTED, "split"),
+    (dict(rho_floor=-1e-6), _abi.DG_ERR_ARG, "floor"),
+    (dict(p_floor=float("nan")), _abi.DG_ERR_ARG, "floor"),
+    (dict(p_floor=float("inf")), _abi.DG_ERR_ARG, "floor"),
+    (dict(physics=_abi.DG_REACTING_EULER, dim=2, nel=(8, 8), rho_floor=1e-6, mech="air5"),
+     _abi.DG_ERR_UNSUPPORTED, "floor"),
 ])
 def test_invalid_descriptors_rejected(kw, code, msg):
     rc, err = create(desc(**kw))
@@ -82,7 +94,8 @@ def test_null_arguments():
 
 @pytest.mark.parametrize("kw", [dict(), dict(volume=_abi.DG_VOLUME_SPLIT),
                                 dict(dim=2, nel=(8, 8), patch=((2, 2), (4, 4)), volume=_abi.DG_VOLUME_SPLIT,
-                                     precision=_abi.DG_F32)])
+                                     precision=_abi.DG_F32),
+                                dict(rho_floor=1e-6, p_floor=5e-7)])
 def test_valid_descriptor_passes_the_checks(kw):
     rc, err = create(desc(**kw))
     # no device here: the only failure left is the device query itself
