@@ -36,6 +36,9 @@ PRESETS = {
     "air5_2d": dict(dim=2, N=3, nel=(64, 64), lo=(-1.0, -1.0), hi=(1.0, 1.0),
                     patch_lo=(24, 24), patch_hi=(40, 40), physics="reacting",
                     cfl=0.5, steps=50, batch=1, mech_seed=42),
+    "air5_2t_2d": dict(dim=2, N=3, nel=(64, 64), lo=(-1.0, -1.0), hi=(1.0, 1.0),
+                       patch_lo=(24, 24), patch_hi=(40, 40), physics="reacting_2t",
+                       cfl=0.5, steps=50, batch=1, mech_seed=42),
     "adjoint3d": dict(dim=3, N=3, nel=(16, 16, 16), lo=(0.0, 0.0, 0.0),
                       hi=(TWO_PI, TWO_PI, TWO_PI), physics="euler", gamma=1.4,
                       cfl=0.5, steps=50, batch=8),
@@ -213,3 +216,51 @@ def reacting_state(coords, lo, hi, mech, rho0=1.0e-3, T0=5000.0, dT=4000.0):
     E = sum(rhos[s] * (mech["cv"][s] * T + mech["h0"][s]) for s in range(mech["ns"]))
     zeros = [np.zeros_like(rho) for _ in range(dim)]
     return np.concatenate([rhos, np.stack(zeros), E[None]])
+
+
+def air5_vibration(mech):
+    """Vibrational data of the air-5 mechanism for the two-temperature model.
+
+    theta_v: characteristic vibrational temperatures of N2, O2 and NO from
+    standard spectroscopic tables (3395, 2239 and 2817 K); the atoms have no
+    vibrational mode (0).  Millikan-White constants of molecule s with
+    collision partner r from the published correlation in the reduced molar
+    mass mu_sr (g/mol): A_sr = 1.16e-3 mu_sr^(1/2) theta_s^(4/3),
+    B_sr = 0.015 mu_sr^(1/4).  Park's limiting cross-section sigma' = 1e-21 m^2.
+    Reactions 0-2 (dissociation) take their rates at sqrt(T T_v), the
+    exchange reactions 3-4 at T."""
+    ns = mech["ns"]
+    theta = np.array([3395.0, 2239.0, 2817.0, 0.0, 0.0])
+    Wg = np.asarray(mech["W"]) * 1.0e3
+    mw_a = np.zeros((ns, ns))
+    mw_b = np.zeros((ns, ns))
+    for s_ in range(ns):
+        if theta[s_] == 0.0:
+            continue
+        for r in range(ns):
+            mu = Wg[s_] * Wg[r] / (Wg[s_] + Wg[r])
+            mw_a[s_, r] = 1.16e-3 * np.sqrt(mu) * theta[s_] ** (4.0 / 3.0)
+            mw_b[s_, r] = 0.015 * mu ** 0.25
+    return dict(theta_v=theta, mw_a=mw_a, mw_b=mw_b, park_sigma=1.0e-21,
+                two_temp=np.array([1, 1, 1, 0, 0], dtype=np.int32))
+
+
+def reacting2t_state(coords, lo, hi, mech, vib, rho0=1.0e-3, T0=5000.0, dT=4000.0, u0=0.0):
+    """Two-temperature reacting state: T, rho, Y_s as in reacting_state, the
+    vibrational energy of each molecule a fraction 0.3 + 0.8 |g_v| (seed 20)
+    of rho_s R_s T (so T_v lies on both sides of T), velocity u0 g_d (seeds
+    21, 22, ...).  Conserved: (rho_s, rho u, E, E_v) with
+    E = sum rho_s (cv_s T + h0_s) + E_v + rho |u|^2 / 2."""
+    dim = coords.shape[0]
+    T = T0 + dT * fourier_field(coords, lo, hi, seed=10)
+    rho = rho0 * (1.0 + 0.05 * fourier_field(coords, lo, hi, seed=11))
+    y = np.stack([0.05 + np.abs(fourier_field(coords, lo, hi, seed=12 + s)) for s in range(mech["ns"])])
+    y = y / y.sum(axis=0, keepdims=True)
+    rhos = rho[None] * y
+    frac = 0.3 + 0.8 * np.abs(fourier_field(coords, lo, hi, seed=20))
+    Ev = sum(rhos[s] * mech["R"][s] * T * frac for s in range(mech["ns"]) if vib["theta_v"][s] > 0.0)
+    vel = [u0 * fourier_field(coords, lo, hi, seed=21 + d) for d in range(dim)]
+    ke = 0.5 * rho * sum(v * v for v in vel)
+    E = sum(rhos[s] * (mech["cv"][s] * T + mech["h0"][s]) for s in range(mech["ns"])) + Ev + ke
+    mom = [rho * v for v in vel]
+    return np.concatenate([rhos, np.stack(mom), E[None], Ev[None]])
