@@ -62,7 +62,10 @@ enum dg_status {
   DG_ERR_NEWTON = 6
 };
 
-enum dg_physics { DG_EULER = 0, DG_NAVIER_STOKES = 1, DG_REACTING_EULER = 2 };
+/* DG_REACTING_EULER: one temperature, vibration frozen.
+ * DG_REACTING_2T: translational-rotational T and vibrational T_v (Thermochemical
+ *   non-equilibrium section): the state gains E_v (last variable). */
+enum dg_physics { DG_EULER = 0, DG_NAVIER_STOKES = 1, DG_REACTING_EULER = 2, DG_REACTING_2T = 3 };
 enum dg_precision { DG_F64 = 0, DG_F32 = 1 };
 
 /* Volume integral of the Euler operator.
@@ -98,13 +101,33 @@ typedef struct dg_mechanism {
   double kappa_c, kappa_r;
 } dg_mechanism;
 
+/* Vibrational data of the two-temperature model (Thermochemical
+ * non-equilibrium section; eq. src_landau_teller).  Harmonic oscillator
+ * e_v,s(T) = R_s theta_v[s] / (exp(theta_v[s]/T) - 1); theta_v = 0 marks a
+ * species without a vibrational mode.  Relaxation time of molecule s:
+ * tau_s = tau_MW + tau_P with the Millikan-White mixture time
+ * 1 / tau_MW = (p / 1 atm) sum_r x_r exp(-(mw_a[s][r] (T^(-1/3) - mw_b[s][r]) - 18.42))
+ * (x_r molar fractions) and Park's correction tau_P = 1 / (sigma_v cbar_s n),
+ * sigma_v = park_sigma (50000 K / T)^2, cbar_s = sqrt(8 R_u T / (pi W_s)),
+ * n = p / (k_B T).  two_temp[r] != 0: reaction r takes its forward and
+ * backward rates at T_a = sqrt(T T_v) (dissociation), else at T.  The
+ * struct is copied by dg_create. */
+typedef struct dg_vibration {
+  double theta_v[DG_MAX_SPECIES];                 /* K */
+  double mw_a[DG_MAX_SPECIES][DG_MAX_SPECIES];    /* K^(1/3) */
+  double mw_b[DG_MAX_SPECIES][DG_MAX_SPECIES];
+  double park_sigma;                              /* m^2 */
+  int32_t two_temp[DG_MAX_REACTIONS];
+} dg_vibration;
+
 /* Problem description.  Periodic box [lo, hi] with nel cells per direction;
  * 2-D only: the coarse block [patch_lo, patch_hi) is refined once (2:1),
  * coupled through mortars (empty when patch_lo == patch_hi).
  * Supported: dim 2 or 3; degree 1..7 (Euler), 2..4 (Navier-Stokes, 3-D),
  * 3 (reacting, 2-D, up to DG_MAX_SPECIES species); batch >= 1.
  * Navier-Stokes uses constant mu, non-dimensional R = 1 (T = p/rho) and
- * k = gamma mu / (Pr (gamma - 1)).  Reacting Euler reads mech (copied). */
+ * k = gamma mu / (Pr (gamma - 1)).  Reacting Euler reads mech (copied); the
+ * two-temperature physics also reads vib (copied). */
 typedef struct dg_desc {
   int32_t dim, degree, physics, precision, batch;
   int32_t nel[3];
@@ -123,6 +146,7 @@ typedef struct dg_desc {
    * p_floor/(gamma-1) + |m|^2/(2 rho) where it lies below.  0 for both turns
    * it off; Euler and Navier-Stokes physics only. */
   double rho_floor, p_floor;
+  const dg_vibration* vib; /* DG_REACTING_2T only; NULL otherwise */
 } dg_desc;
 
 /* Sticky device-side counters (dg_status_read). */

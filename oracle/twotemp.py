@@ -283,13 +283,14 @@ def implicit_substep(phys, U, h, max_iter=25, tol=1e-13, max_halvings=30):
             alpha = torch.where(bad, 0.5 * alpha, alpha)
         n0 = (R0.abs() / sca).max(dim=0).values
         for _ in range(max_halvings + 1):
-            Yt = torch.clamp(Ya + alpha * dY, min=0.0)
+            used = alpha
+            Yt = torch.clamp(Ya + used * dY, min=0.0)
             Rt, Tt = residual(Yt, Yna, kea, Ea)
-            bad = ~done & ((Rt.abs() / sca).max(dim=0).values > (1.0 - 1e-4 * alpha) * n0)
+            bad = ~done & ((Rt.abs() / sca).max(dim=0).values > (1.0 - 1e-4 * used) * n0)
             if not bool(bad.any()):
                 break
             alpha = torch.where(bad, 0.5 * alpha, alpha)
-        clips += int((Ya + alpha * dY < 0).sum())
+        clips += int((Ya + used * dY < 0).sum())
         Y[:, idx] = Yt
         R[:, idx] = Rt
         T[idx] = Tt

@@ -15,7 +15,7 @@ DG_MAX_SPECIES = 8
 DG_MAX_REACTIONS = 8
 
 DG_OK, DG_ERR_ARG, DG_ERR_UNSUPPORTED, DG_ERR_HIP, DG_ERR_OOM, DG_ERR_NONPHYSICAL, DG_ERR_NEWTON = range(7)
-DG_EULER, DG_NAVIER_STOKES, DG_REACTING_EULER = range(3)
+DG_EULER, DG_NAVIER_STOKES, DG_REACTING_EULER, DG_REACTING_2T = range(4)
 DG_F64, DG_F32 = range(2)
 DG_VOLUME_STANDARD, DG_VOLUME_SPLIT = range(2)
 
@@ -44,6 +44,16 @@ class Mechanism(ctypes.Structure):
     ]
 
 
+class Vibration(ctypes.Structure):
+    _fields_ = [
+        ("theta_v", c_double * DG_MAX_SPECIES),
+        ("mw_a", (c_double * DG_MAX_SPECIES) * DG_MAX_SPECIES),
+        ("mw_b", (c_double * DG_MAX_SPECIES) * DG_MAX_SPECIES),
+        ("park_sigma", c_double),
+        ("two_temp", c_int32 * DG_MAX_REACTIONS),
+    ]
+
+
 class Desc(ctypes.Structure):
     _fields_ = [
         ("dim", c_int32), ("degree", c_int32), ("physics", c_int32), ("precision", c_int32),
@@ -54,6 +64,7 @@ class Desc(ctypes.Structure):
         ("newton_max_iter", c_int32), ("newton_tol", c_double), ("device", c_int32),
         ("volume", c_int32),
         ("rho_floor", c_double), ("p_floor", c_double),
+        ("vib", POINTER(Vibration)),
     ]
 
 

@@ -377,7 +377,7 @@ __global__ void k_reset_counters(int* cnt, unsigned long long* first_bad) {
 
 void free_ctx(Ctx& c) {
   void* ptrs[] = {c.d_nbr, c.d_geo, c.d_K, c.d_counters, c.d_first_bad, c.d_mortars,
-                  c.d_mortar_flux, c.d_red, c.d_red_out, c.d_face, c.d_mech, c.d_corner};
+                  c.d_mortar_flux, c.d_red, c.d_red_out, c.d_face, c.d_mech, c.d_vib, c.d_corner};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -421,7 +421,7 @@ int dg_create(const dg_desc* desc, dg_ctx** out) {
     if (d.nel[l] < 1) return fail(DG_ERR_ARG, "nel must be >= 1");
     if (!(d.hi[l] > d.lo[l])) return fail(DG_ERR_ARG, "hi must exceed lo");
   }
-  if (!(d.gamma > 1.0) && d.physics != DG_REACTING_EULER) return fail(DG_ERR_ARG, "gamma must exceed 1");
+  if (!(d.gamma > 1.0) && !is_reacting(d.physics)) return fail(DG_ERR_ARG, "gamma must exceed 1");
   {
     // one batch member's state is addressed with 32-bit byte offsets
     const long double n1 = d.degree + 1.0L;
@@ -429,7 +429,8 @@ int dg_create(const dg_desc* desc, dg_ctx** out) {
     for (int l = 0; l < d.dim; ++l) elems *= d.nel[l];
     if (d.dim == 2 && (d.patch_lo[0] != d.patch_hi[0] || d.patch_lo[1] != d.patch_hi[1]))
       elems += 3.0L * (d.patch_hi[0] - d.patch_lo[0]) * (d.patch_hi[1] - d.patch_lo[1]);
-    const int nvars = d.physics == DG_REACTING_EULER ? (d.mech ? d.mech->nspecies : 0) + d.dim + 1 : d.dim + 2;
+    const int nvars = is_reacting(d.physics) ? (d.mech ? d.mech->nspecies : 0) + d.dim + 1 + (d.physics == DG_REACTING_2T)
+                                             : d.dim + 2;
     const long double bytes = elems * (d.dim == 3 ? n1 * n1 * n1 : n1 * n1) * nvars * (d.precision == DG_F32 ? 4 : 8);
     if (elems > 2147483647.0L || bytes >= 4294967296.0L)
       return fail(DG_ERR_UNSUPPORTED, "one batch member's state must stay below 4 GiB (32-bit addressing)");
@@ -451,15 +452,22 @@ int dg_create(const dg_desc* desc, dg_ctx** out) {
       if (!(d.mu >= 0.0) || !(d.prandtl > 0.0)) return fail(DG_ERR_ARG, "mu >= 0 and prandtl > 0 required");
       break;
     case DG_REACTING_EULER:
+    case DG_REACTING_2T:
       if (d.dim != 2 || d.degree != 3) return fail(DG_ERR_UNSUPPORTED, "reacting Euler: 2-D, degree 3");
       if (!d.mech || d.mech->nspecies != 5 || d.mech->nreactions != 5)
         return fail(DG_ERR_UNSUPPORTED, "reacting Euler: mechanism with 5 species and 5 reactions");
+      if (d.physics == DG_REACTING_2T) {
+        if (!d.vib) return fail(DG_ERR_ARG, "two-temperature physics needs vibrational data (vib)");
+        for (int q = 0; q < d.mech->nspecies; ++q)
+          if (!(d.vib->theta_v[q] >= 0.0)) return fail(DG_ERR_ARG, "vib: theta_v must be >= 0");
+        if (!(d.vib->park_sigma > 0.0)) return fail(DG_ERR_ARG, "vib: park_sigma must be > 0");
+      }
       break;
     default: return fail(DG_ERR_ARG, "unknown physics");
   }
   if (!(d.rho_floor >= 0.0) || !(d.p_floor >= 0.0) || !std::isfinite(d.rho_floor) || !std::isfinite(d.p_floor))
     return fail(DG_ERR_ARG, "rho_floor and p_floor must be finite and >= 0");
-  if ((d.rho_floor > 0.0 || d.p_floor > 0.0) && d.physics == DG_REACTING_EULER)
+  if ((d.rho_floor > 0.0 || d.p_floor > 0.0) && is_reacting(d.physics))
     return fail(DG_ERR_UNSUPPORTED, "positivity floor: Euler and Navier-Stokes physics only");
   if (d.volume != DG_VOLUME_STANDARD && d.volume != DG_VOLUME_SPLIT)
     return fail(DG_ERR_ARG, "volume must be DG_VOLUME_STANDARD or DG_VOLUME_SPLIT");
@@ -475,14 +483,17 @@ int dg_create(const dg_desc* desc, dg_ctx** out) {
   c.desc = d;
   c.desc.mech = nullptr;
   std::memset(&c.mech, 0, sizeof(c.mech));
-  if (d.physics == DG_REACTING_EULER) c.mech = *d.mech;
+  std::memset(&c.vib, 0, sizeof(c.vib));
+  if (is_reacting(d.physics)) c.mech = *d.mech;
+  if (d.physics == DG_REACTING_2T) c.vib = *d.vib;
+  c.desc.vib = nullptr;
   if (c.desc.newton_max_iter <= 0) c.desc.newton_max_iter = 25;
   if (!(c.desc.newton_tol > 0.0)) c.desc.newton_tol = 1e-13;
   c.dim = d.dim;
   c.N = d.degree;
   c.n = d.degree + 1;
   c.Np = c.dim == 2 ? c.n * c.n : c.n * c.n * c.n;
-  c.nv = d.physics == DG_REACTING_EULER ? c.mech.nspecies + c.dim + 1 : c.dim + 2;
+  c.nv = is_reacting(d.physics) ? c.mech.nspecies + c.dim + 1 + (d.physics == DG_REACTING_2T) : c.dim + 2;
   c.B = d.batch;
   c.device = d.device;
   std::memset(&c.pc, 0, sizeof(c.pc));
@@ -534,8 +545,9 @@ int dg_create(const dg_desc* desc, dg_ctx** out) {
       return hip_fail(e, "dg_create mortars");
     }
   }
-  if (d.physics == DG_REACTING_EULER) {
-    if ((e = upload(&c.d_mech, &c.mech, sizeof(dg_mechanism))) != hipSuccess) {
+  if (is_reacting(d.physics)) {
+    if ((e = upload(&c.d_mech, &c.mech, sizeof(dg_mechanism))) != hipSuccess ||
+        (d.physics == DG_REACTING_2T && (e = upload(&c.d_vib, &c.vib, sizeof(dg_vibration))) != hipSuccess)) {
       free_ctx(c);
       delete ctx;
       return hip_fail(e, "dg_create mechanism");
@@ -688,7 +700,7 @@ int dg_ssprk54_step(dg_ctx* ctx, void* U, double dt, void* t1, void* t2, void* t
 int dg_source_chem(dg_ctx* ctx, const void* U, void* out, double h, int32_t mode, void* stream) {
   if (!ctx || !U || !out) return fail(DG_ERR_ARG, "dg_source_chem: null argument");
   Ctx& c = ctx->c;
-  if (c.desc.physics != DG_REACTING_EULER) return fail(DG_ERR_UNSUPPORTED, "dg_source_chem: reacting Euler only");
+  if (!is_reacting(c.desc.physics)) return fail(DG_ERR_UNSUPPORTED, "dg_source_chem: reacting Euler only");
   if (mode != 0 && mode != 1) return fail(DG_ERR_ARG, "dg_source_chem: mode must be 0 or 1");
   if (out != U && overlaps(U, out, state_bytes(c))) return fail(DG_ERR_ARG, "dg_source_chem: partial overlap");
   DeviceGuard guard(c.device);

@@ -171,9 +171,12 @@ struct EulerPhys {
 // Reacting Euler, one temperature: U = (rho_1..rho_NS, m, E).
 //   E = sum rho_s cv_s T + |m|^2/(2 rho) + sum rho_s h0_s,  p = T sum rho_s R_s,
 //   frozen sound speed a^2 = (1 + sum rho_s R_s / sum rho_s cv_s) p / rho.
-template <int DIM, int NS>
+// Two temperatures (TWO_T): U = (rho_1..rho_NS, m, E, E_v), the vibrational
+// energy E_v taken out of E before T is recovered and advected as E_v u_l.
+template <int DIM, int NS, bool TWO_T = false>
 struct ReactPhys {
-  static constexpr int NV = NS + DIM + 1;
+  // (rho_1..rho_NS, m_1..m_DIM, E) and, with two temperatures, E_v last
+  static constexpr int NV = NS + DIM + 1 + (TWO_T ? 1 : 0);
   static constexpr int MOM = NS;
   static constexpr int NDIM = DIM;
   __device__ static __forceinline__ bool thermo(const double (&U)[NV], Thermo& t, const PhysConst& c) {
@@ -190,7 +193,9 @@ struct ReactPhys {
 #pragma unroll
     for (int d = 0; d < DIM; ++d) m2 = fma(U[NS + d], U[NS + d], m2);
     const double cvi = frcp(cv);
-    const double T = (fma(-0.5 * m2, t.ri, U[NS + DIM]) - h0) * cvi;
+    // translational-rotational energy: the vibrational energy E_v is its own variable
+    const double e_tr = TWO_T ? U[NS + DIM] - U[NS + DIM + 1] : U[NS + DIM];
+    const double T = (fma(-0.5 * m2, t.ri, e_tr) - h0) * cvi;
     t.p = T * Rm;
     t.k = fma(Rm, cvi, 1.0);
     return (rho > 0.0) && (T > 0.0) && (t.p > 0.0);
@@ -202,6 +207,7 @@ struct ReactPhys {
     for (int d = 0; d < DIM; ++d) F[NS + d] = U[NS + d] * ul;
     F[NS + l] += p;
     F[NS + DIM] = (U[NS + DIM] + p) * ul;
+    if constexpr (TWO_T) F[NS + DIM + 1] = U[NS + DIM + 1] * ul;
   }
 };
 

@@ -74,6 +74,7 @@ struct StageParams {
 struct Ctx {
   dg_desc desc;
   dg_mechanism mech;
+  dg_vibration vib;              // two-temperature physics only (zeroed otherwise)
   int dim, N, n, Np, nv, E, B;
   int device;
   double hmin;
@@ -95,11 +96,14 @@ struct Ctx {
   double* d_red_out = nullptr;   // final reduction results
   void* d_face = nullptr;        // BR1 face buffer
   void* d_mech = nullptr;        // mechanism copy on device
+  void* d_vib = nullptr;         // vibrational data on device (two-temperature)
   std::vector<double> h_corner;  // host copy [E][3] lower corners (coords)
   std::vector<double> h_geo;     // host copy [E][4]
 };
 
 MeshView mesh_view(const Ctx& c);
+
+inline bool is_reacting(int physics) { return physics == DG_REACTING_EULER || physics == DG_REACTING_2T; }
 
 // ---- launchers (return hipError_t of the launch) ---------------------------
 hipError_t launch_stage(const Ctx& c, const StageParams& sp, hipStream_t s);

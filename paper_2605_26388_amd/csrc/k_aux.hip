@@ -104,7 +104,7 @@ k_final_sum(const double* partial, int nparts, int nq, double* out) {
 }
 
 hipError_t launch_integrals(const Ctx& c, const void* U, double* d_out, hipStream_t s) {
-  const int nspec = c.desc.physics == DG_REACTING_EULER ? c.mech.nspecies : 1;
+  const int nspec = is_reacting(c.desc.physics) ? c.mech.nspecies : 1;
   dim3 grid(RED_BLOCKS, c.B);
   if (c.desc.precision == DG_F32)
     hipLaunchKernelGGL((k_integrals<float>), grid, dim3(RED_BS), 0, s, static_cast<const float*>(U), c.dim, c.n,
@@ -198,6 +198,9 @@ static hipError_t lam_t(const Ctx& c, const void* U, double* d_out, hipStream_t 
   const int nb = RED_BLOCKS;
   if (c.desc.physics == DG_REACTING_EULER)
     hipLaunchKernelGGL((k_lam_max<T, ReactPhys<2, 5>>), dim3(nb), dim3(RED_BS), 0, s, Ut, c.E, c.Np, c.B, c.pc, c.d_red);
+  else if (c.desc.physics == DG_REACTING_2T)
+    hipLaunchKernelGGL((k_lam_max<T, ReactPhys<2, 5, true>>), dim3(nb), dim3(RED_BS), 0, s, Ut, c.E, c.Np, c.B, c.pc,
+                       c.d_red);
   else if (c.dim == 2)
     hipLaunchKernelGGL((k_lam_max<T, EulerPhys<2>>), dim3(nb), dim3(RED_BS), 0, s, Ut, c.E, c.Np, c.B, c.pc, c.d_red);
   else

@@ -238,12 +238,339 @@ k_source(const T* U, T* out, const dg_mechanism* mech, size_t plane, int B, doub
   }
 }
 
+// ---------------------------------------------------------------------------
+// Two temperatures (Thermochemical non-equilibrium section; eqs.
+// src_reaction_rate, src_omega, src_landau_teller, source_residual).  State
+// (rho_s, m, E, E_v).  Per node:
+//   T   from E - E_v - |m|^2/(2 rho) - sum rho_s h0_s = T sum rho_s cv_s;
+//   T_v from E_v = sum_mol rho_s e_v,s(T_v), e_v,s = R_s theta_s / (exp(theta_s/T) - 1),
+//       by Newton in ln T_v from the inverse of a single mode with the
+//       mixture's mean theta (exact when the thetas agree; a few steps);
+//   rates of reaction r at T_a = sqrt(T T_v) when flagged (dissociation),
+//       else at T;
+//   Q_T-v = sum_mol rho_s (e_v,s(T) - e_v,s(T_v)) / tau_s with the
+//       Millikan-White mixture time plus Park's correction;
+//   S_Ev = Q_T-v + sum_mol wdot_s e_v,s(T_v).
+// Implicit substep on Y = (rho_s, E_v): Newton with the one-sided difference
+// Jacobian and Gauss-Jordan, globalised as follows: the step length alpha is
+// halved while the clipped update would move T outside [T/2, 2T], then
+// further until the scaled residual max_k |R_k|/scale_k falls by
+// (1 - 1e-4 alpha) (at most 30 halvings each); the accepted update's residual
+// is the next iteration's; converged when the undamped step satisfies
+// max_k |dY_k|/scale_k <= tol (then applied in full); scale = rho for the
+// species and E - |m|^2/(2 rho) - sum rho_s h0_s for E_v; rho_s and E_v are
+// clipped at 0 (counted).
+// ---------------------------------------------------------------------------
+constexpr double kRUniversal = 8.31446261815324;  // J/(mol K)
+constexpr double kBoltzmann = 1.380649e-23;       // J/K
+constexpr double kAtm = 101325.0;                 // Pa
+constexpr double kPi = 3.14159265358979323846;
+
+template <int NS, int NR>
+struct Chem2T {
+  const dg_mechanism* m;
+  const dg_vibration* v;
+
+  __device__ __forceinline__ double temperature(const double (&Y)[NS + 1], double ke, double E) const {
+    double cv = 0.0, h0 = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      cv = fma(Y[s], m->cv[s], cv);
+      h0 = fma(Y[s], m->h0[s], h0);
+    }
+    return (E - Y[NS] - ke - h0) / cv;
+  }
+
+  __device__ __forceinline__ double ev(int s, double T) const {
+    const double th = v->theta_v[s];
+    return th > 0.0 ? m->R[s] * th / expm1(th / T) : 0.0;
+  }
+
+  // T_v with sum_mol rho_s e_v,s(T_v) = Ev (1 K for Ev <= 0, 1e6 K without molecules)
+  __device__ __forceinline__ double t_vib(const double (&Y)[NS + 1]) const {
+    const double Ev = Y[NS];
+    if (!(Ev > 0.0)) return 1.0;
+    double A = 0.0, B = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const double th = v->theta_v[s];
+      if (th > 0.0) {
+        const double a = Y[s] * m->R[s];
+        A = fma(a, th, A);
+        B += a;
+      }
+    }
+    if (!(B > 0.0)) return 1.0e6;
+    double T = (A / B) / log1p(A / Ev);
+    for (int it = 0; it < 40; ++it) {
+      double f = -Ev, fp = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const double th = v->theta_v[s];
+        if (th > 0.0) {
+          const double x = th / T;
+          const double em = expm1(x);
+          const double a = Y[s] * m->R[s];
+          f = fma(a, th / em, f);
+          fp = fma(a * x * x, (em + 1.0) / (em * em), fp);  // d/dT of rho_s e_v,s
+        }
+      }
+      const double dl = f / (T * fp);  // Newton step in ln T
+      T *= exp(-dl);
+      if (fabs(dl) <= 1e-12) break;
+    }
+    return T;
+  }
+
+  __device__ __forceinline__ void wdot(const double (&Y)[NS + 1], double T, double Tv, double (&w)[NS]) const {
+    double X[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      X[s] = m->kappa_c * Y[s] / m->W[s];
+      w[s] = 0.0;
+    }
+    const double lnT = log(T);
+    const double Ti = 1.0 / T;
+    const double Ta = sqrt(T * Tv);
+    const double lnTa = log(Ta);
+    const double Tai = 1.0 / Ta;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const bool two = v->two_temp[r] != 0;
+      const double lt = two ? lnTa : lnT;
+      const double ti = two ? Tai : Ti;
+      double fwd = m->A_f[r] * exp(fma(m->beta_f[r], lt, -m->theta_f[r] * ti));
+      double bwd = 0.0;
+      for (int s = 0; s < NS; ++s)
+        for (int q = 0; q < m->nu_f[r][s]; ++q) fwd *= X[s];
+      if (m->reversible[r]) {
+        bwd = m->A_b[r] * exp(fma(m->beta_b[r], lt, -m->theta_b[r] * ti));
+        for (int s = 0; s < NS; ++s)
+          for (int q = 0; q < m->nu_b[r][s]; ++q) bwd *= X[s];
+      }
+      double M = 1.0;
+      if (m->third_body[r]) {
+        M = 0.0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) M = fma(m->eff[r][s], X[s], M);
+      }
+      const double Rr = M * (fwd - bwd);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int dnu = m->nu_b[r][s] - m->nu_f[r][s];
+        if (dnu != 0) w[s] = fma(m->kappa_r * m->W[s] * dnu, Rr, w[s]);
+      }
+    }
+  }
+
+  // Landau-Teller term at densities Y, temperatures T, T_v
+  __device__ __forceinline__ double q_vt(const double (&Y)[NS + 1], double T, double Tv) const {
+    double moles[NS], ntot = 0.0, Rm = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      moles[s] = Y[s] / m->W[s];
+      ntot += moles[s];
+      Rm = fma(Y[s], m->R[s], Rm);
+    }
+    const double p = T * Rm;
+    const double patm = p / kAtm;
+    const double n = p / (kBoltzmann * T);
+    const double sig = v->park_sigma * (50000.0 / T) * (50000.0 / T);
+    const double Tm13 = exp(-log(T) / 3.0);
+    double q = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      if (!(v->theta_v[s] > 0.0)) continue;
+      double inv = 0.0;
+#pragma unroll
+      for (int r = 0; r < NS; ++r)
+        inv = fma(moles[r] / ntot, exp(-(v->mw_a[s][r] * (Tm13 - v->mw_b[s][r]) - 18.42)), inv);
+      const double tau_mw = 1.0 / (patm * inv);
+      const double cbar = sqrt(8.0 * kRUniversal * T / (kPi * m->W[s]));
+      const double tau = tau_mw + 1.0 / (sig * cbar * n);
+      q += Y[s] * (ev(s, T) - ev(s, Tv)) / tau;
+    }
+    return q;
+  }
+
+  // S_Y = (wdot_s, Q_T-v + sum_mol wdot_s e_v,s(T_v)) at Y with temperature T
+  __device__ __forceinline__ void source(const double (&Y)[NS + 1], double T, double (&S)[NS + 1]) const {
+    const double Tv = t_vib(Y);
+    double w[NS];
+    wdot(Y, T, Tv, w);
+    double sev = q_vt(Y, T, Tv);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      S[s] = w[s];
+      if (v->theta_v[s] > 0.0) sev = fma(w[s], ev(s, Tv), sev);
+    }
+    S[NS] = sev;
+  }
+
+  // R(Y) = Y - Yn - h S_Y(Y); returns T(Y)
+  __device__ __forceinline__ double residual(const double (&Y)[NS + 1], const double (&Yn)[NS + 1], double h,
+                                             double ke, double E, double (&R)[NS + 1]) const {
+    const double T = temperature(Y, ke, E);
+    double S[NS + 1];
+    source(Y, T, S);
+#pragma unroll
+    for (int k = 0; k <= NS; ++k) R[k] = (Y[k] - Yn[k]) - h * S[k];
+    return T;
+  }
+};
+
+template <typename T, int NS, int NR, int DIM>
+__global__ void __launch_bounds__(256)
+k_source2t(const T* U, T* out, const dg_mechanism* mech, const dg_vibration* vib, size_t plane, int B, double h,
+           int mode, int max_iter, double tol, int* counters, unsigned long long* first_bad) {
+  constexpr int NV = NS + DIM + 2;
+  constexpr int NY = NS + 1;
+  const Chem2T<NS, NR> chem{mech, vib};
+  const size_t total = plane * B;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+    const size_t b = t / plane;
+    const size_t r = t - b * plane;
+    const size_t base = b * NV * plane + r;
+    double Yn[NY], mom[DIM];
+    double rho = 0.0, h0 = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      Yn[s] = static_cast<double>(U[base + s * plane]);
+      rho += Yn[s];
+      h0 = fma(Yn[s], mech->h0[s], h0);
+    }
+    Yn[NS] = static_cast<double>(U[base + (NS + DIM + 1) * plane]);
+    double m2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      mom[d] = static_cast<double>(U[base + (NS + d) * plane]);
+      m2 += mom[d] * mom[d];
+    }
+    const double E = static_cast<double>(U[base + (NS + DIM) * plane]);
+    const double ke = 0.5 * m2 / rho;
+    if (mode == 0) {
+      const double Tn = chem.temperature(Yn, ke, E);
+      if (!(Tn > 0.0) || !(Yn[NS] >= 0.0)) report_nonphysical(counters, first_bad, t);
+      double S[NY];
+      chem.source(Yn, Tn, S);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const double o = static_cast<double>(out[base + s * plane]);
+        out[base + s * plane] = static_cast<T>(o + S[s]);
+      }
+      const size_t iv = base + (NS + DIM + 1) * plane;
+      out[iv] = static_cast<T>(static_cast<double>(out[iv]) + S[NS]);
+      continue;
+    }
+    // ---- implicit substep ----------------------------------------------------
+    double scale[NY];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) scale[s] = rho;
+    scale[NS] = fabs(E - ke - h0);
+    double Y[NY], R0[NY];
+#pragma unroll
+    for (int k = 0; k < NY; ++k) Y[k] = Yn[k];
+    double T0 = chem.residual(Y, Yn, h, ke, E, R0);
+    bool converged = false, bad_state = false;
+    int it = 0, clips = 0;
+    for (; it < max_iter; ++it) {
+      if (!(T0 > 0.0)) {
+        bad_state = true;
+        break;
+      }
+      double J[NY][NY];
+#pragma unroll
+      for (int k = 0; k < NY; ++k) {
+        const double eps = fmax(1e-7 * fabs(Y[k]), 1e-12);
+        double Yp[NY], Rk[NY];
+#pragma unroll
+        for (int q = 0; q < NY; ++q) Yp[q] = Y[q];
+        Yp[k] = Yp[k] + eps;
+        chem.residual(Yp, Yn, h, ke, E, Rk);
+#pragma unroll
+        for (int q = 0; q < NY; ++q) J[q][k] = (Rk[q] - R0[q]) / eps;
+      }
+      double rhs[NY], dY[NY];
+#pragma unroll
+      for (int k = 0; k < NY; ++k) rhs[k] = -R0[k];
+      gauss_jordan<NY>(J, rhs, dY);
+      double dn = 0.0, n0 = 0.0;
+#pragma unroll
+      for (int k = 0; k < NY; ++k) {
+        dn = fmax(dn, fabs(dY[k]) / scale[k]);
+        n0 = fmax(n0, fabs(R0[k]) / scale[k]);
+      }
+      const bool done = dn <= tol;
+      double alpha = 1.0;
+      if (!done) {
+        for (int hv = 0; hv < 30; ++hv) {
+          double Yt[NY];
+#pragma unroll
+          for (int k = 0; k < NY; ++k) Yt[k] = fmax(Y[k] + alpha * dY[k], 0.0);
+          const double Tt = chem.temperature(Yt, ke, E);
+          if (!(Tt < 0.5 * T0) && !(Tt > 2.0 * T0)) break;
+          alpha *= 0.5;
+        }
+      }
+      double Yt[NY], Rt[NY], Tt = T0, used = alpha;
+      for (int hv = 0; hv <= 30; ++hv) {
+        used = alpha;
+#pragma unroll
+        for (int k = 0; k < NY; ++k) Yt[k] = fmax(Y[k] + used * dY[k], 0.0);
+        Tt = chem.residual(Yt, Yn, h, ke, E, Rt);
+        if (done) break;
+        double nt = 0.0;
+#pragma unroll
+        for (int k = 0; k < NY; ++k) nt = fmax(nt, fabs(Rt[k]) / scale[k]);
+        if (!(nt > (1.0 - 1e-4 * used) * n0)) break;
+        alpha *= 0.5;
+      }
+#pragma unroll
+      for (int k = 0; k < NY; ++k) {
+        if (Y[k] + used * dY[k] < 0.0) ++clips;
+        Y[k] = Yt[k];
+        R0[k] = Rt[k];
+      }
+      T0 = Tt;
+      if (done) {
+        converged = true;
+        ++it;
+        break;
+      }
+    }
+    if (bad_state) report_nonphysical(counters, first_bad, t);
+    if (!converged) atomicAdd(&counters[CNT_NEWTON], 1);
+    if (clips) atomicAdd(&counters[CNT_CLIPS], clips);
+    atomicMax(&counters[CNT_ITERS], it);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) out[base + s * plane] = static_cast<T>(Y[s]);
+    out[base + (NS + DIM + 1) * plane] = static_cast<T>(Y[NS]);
+    if (out != U) {
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) out[base + (NS + d) * plane] = static_cast<T>(mom[d]);
+      out[base + (NS + DIM) * plane] = static_cast<T>(E);
+    }
+  }
+}
+
 hipError_t launch_source(const Ctx& c, const void* U, void* out, double h, int mode, hipStream_t s) {
   if (c.dim != 2 || c.mech.nspecies != 5 || c.mech.nreactions != 5) return hipErrorNotSupported;
   const size_t plane = (size_t)c.E * c.Np;
   const size_t total = plane * c.B;
   const int blocks = (int)std::min<size_t>((total + 255) / 256, 65535);
   const dg_mechanism* m = static_cast<const dg_mechanism*>(c.d_mech);
+  if (c.desc.physics == DG_REACTING_2T) {
+    const dg_vibration* v = static_cast<const dg_vibration*>(c.d_vib);
+    if (c.desc.precision == DG_F32)
+      hipLaunchKernelGGL((k_source2t<float, 5, 5, 2>), dim3(blocks), dim3(256), 0, s, static_cast<const float*>(U),
+                         static_cast<float*>(out), m, v, plane, c.B, h, mode, c.desc.newton_max_iter,
+                         c.desc.newton_tol, c.d_counters, c.d_first_bad);
+    else
+      hipLaunchKernelGGL((k_source2t<double, 5, 5, 2>), dim3(blocks), dim3(256), 0, s, static_cast<const double*>(U),
+                         static_cast<double*>(out), m, v, plane, c.B, h, mode, c.desc.newton_max_iter,
+                         c.desc.newton_tol, c.d_counters, c.d_first_bad);
+    return hipGetLastError();
+  }
   if (c.desc.precision == DG_F32)
     hipLaunchKernelGGL((k_source<float, 5, 5, 2>), dim3(blocks), dim3(256), 0, s, static_cast<const float*>(U),
                        static_cast<float*>(out), m, plane, c.B, h, mode, c.desc.newton_max_iter, c.desc.newton_tol,

@@ -611,6 +611,11 @@ static hipError_t stage_t(const Ctx& c, const StageParams& sp, hipStream_t s) {
     if (c.dim == 2 && c.N == 3 && c.mech.nspecies == 5) return go<2, 3, ReactPhys<2, 5>, T, true, false>(c, sp, s);
     return hipErrorInvalidValue;
   }
+  if (c.desc.physics == DG_REACTING_2T) {
+    if (c.dim == 2 && c.N == 3 && c.mech.nspecies == 5)
+      return go<2, 3, ReactPhys<2, 5, true>, T, true, false>(c, sp, s);
+    return hipErrorInvalidValue;
+  }
   if (c.desc.volume == DG_VOLUME_SPLIT) {
     if (c.dim == 2) return go_n<2, EulerPhys<2>, T, true, true>(c, sp, s);
     return go_n<3, EulerPhys<3>, T, false, true>(c, sp, s);
@@ -627,12 +632,14 @@ template <typename T>
 static hipError_t mortar_t(const Ctx& c, const void* U, hipStream_t s) {
   const T* Ut = static_cast<const T*>(U);
   dim3 grid(c.nmortar, c.B);
-  if (c.desc.physics == DG_REACTING_EULER) {
-    if (c.N == 3) {
+  if (is_reacting(c.desc.physics)) {
+    if (c.N != 3) return hipErrorInvalidValue;
+    if (c.desc.physics == DG_REACTING_2T)
+      hipLaunchKernelGGL((k_mortar<3, ReactPhys<2, 5, true>, T>), grid, dim3(64), 0, s, c.d_mortars, Ut, mesh_view(c),
+                         c.pc);
+    else
       hipLaunchKernelGGL((k_mortar<3, ReactPhys<2, 5>, T>), grid, dim3(64), 0, s, c.d_mortars, Ut, mesh_view(c), c.pc);
-      return hipGetLastError();
-    }
-    return hipErrorInvalidValue;
+    return hipGetLastError();
   }
   switch (c.N) {
 #define DG_MORTAR_CASE(NN)                                                                                      \

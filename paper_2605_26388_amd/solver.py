@@ -13,7 +13,8 @@ import torch
 from . import _abi
 from ._abi import check
 
-PHYSICS = {"euler": _abi.DG_EULER, "navier_stokes": _abi.DG_NAVIER_STOKES, "reacting": _abi.DG_REACTING_EULER}
+PHYSICS = {"euler": _abi.DG_EULER, "navier_stokes": _abi.DG_NAVIER_STOKES, "reacting": _abi.DG_REACTING_EULER,
+           "reacting_2t": _abi.DG_REACTING_2T}
 PRECISION = {"f64": _abi.DG_F64, "f32": _abi.DG_F32}
 VOLUME = {"standard": _abi.DG_VOLUME_STANDARD, "split": _abi.DG_VOLUME_SPLIT}
 
@@ -39,6 +40,21 @@ def mechanism_struct(mech):
     return m
 
 
+def vibration_struct(vib):
+    """dg_vibration from a vibrational-data dict (see dginputs.air5_vibration)."""
+    v = _abi.Vibration()
+    for s, th in enumerate(vib["theta_v"]):
+        v.theta_v[s] = float(th)
+    for s, row in enumerate(vib["mw_a"]):
+        for r, a in enumerate(row):
+            v.mw_a[s][r] = float(a)
+            v.mw_b[s][r] = float(vib["mw_b"][s][r])
+    v.park_sigma = float(vib["park_sigma"])
+    for r, f in enumerate(vib["two_temp"]):
+        v.two_temp[r] = int(f)
+    return v
+
+
 def _stream(device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
@@ -48,7 +64,8 @@ class Solver:
 
     def __init__(self, dim, degree, nel, lo, hi, physics="euler", precision="f64", batch=1,
                  patch_lo=None, patch_hi=None, gamma=1.4, mu=0.0, prandtl=0.72, mech=None,
-                 newton_max_iter=25, newton_tol=1e-13, device=0, volume="standard", rho_floor=0.0, p_floor=0.0):
+                 newton_max_iter=25, newton_tol=1e-13, device=0, volume="standard", rho_floor=0.0, p_floor=0.0,
+                 vib=None):
         self.lib = _abi.load()
         d = _abi.Desc()
         d.dim, d.degree = int(dim), int(degree)
@@ -69,6 +86,8 @@ class Solver:
         d.device = int(device)
         d.volume = VOLUME[volume]
         d.rho_floor, d.p_floor = float(rho_floor), float(p_floor)
+        self._vib = vibration_struct(vib) if vib is not None else None
+        d.vib = ctypes.pointer(self._vib) if self._vib is not None else None
         self.device = torch.device("cuda", int(device))
         self.dim, self.N, self.batch = int(dim), int(degree), int(batch)
         self.physics, self.precision, self.volume = physics, precision, volume

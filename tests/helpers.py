@@ -13,13 +13,16 @@ from oracle.physics import Euler, ReactingEuler
 
 
 def make_pair(dim, N, nel, lo, hi, physics="euler", precision="f64", batch=1, patch=None,
-              mu=0.0, prandtl=0.72, mech=None, volume="standard"):
+              mu=0.0, prandtl=0.72, mech=None, volume="standard", vib=None):
     from paper_2605_26388_amd import Solver
     plo, phi = patch if patch else (None, None)
     mesh = cartesian_mesh(dim, N, nel, lo, hi, plo, phi)
     viscous = None
     if physics == "reacting":
         phys = ReactingEuler(dim, mech)
+    elif physics == "reacting_2t":
+        from oracle.twotemp import ReactingEuler2T
+        phys = ReactingEuler2T(dim, mech, vib)
     else:
         phys = Euler(dim)
         if physics == "navier_stokes":
@@ -29,7 +32,7 @@ def make_pair(dim, N, nel, lo, hi, physics="euler", precision="f64", batch=1, pa
     else:
         op = Operator(mesh, phys, viscous=viscous)
     s = Solver(dim, N, nel, lo, hi, physics=physics, precision=precision, batch=batch,
-               patch_lo=plo, patch_hi=phi, mu=mu, prandtl=prandtl, mech=mech, volume=volume)
+               patch_lo=plo, patch_hi=phi, mu=mu, prandtl=prandtl, mech=mech, volume=volume, vib=vib)
     assert s.E == mesh.E
     return op, s
 

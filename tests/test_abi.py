@@ -54,6 +54,8 @@ int main(void) {
          offsetof(dg_desc, newton_tol), offsetof(dg_desc, device), offsetof(dg_desc, patch_hi),
          offsetof(dg_desc, volume));
   printf("%zu %zu %zu\n", offsetof(dg_desc, rho_floor), offsetof(dg_desc, p_floor), offsetof(dg_counters, floored));
+  printf("%zu %zu %zu %zu\n", offsetof(dg_desc, vib), sizeof(dg_vibration), offsetof(dg_vibration, park_sigma),
+         offsetof(dg_vibration, two_temp));
   printf("%zu %zu %zu\n", offsetof(dg_mechanism, nu_f), offsetof(dg_mechanism, eff),
          offsetof(dg_mechanism, kappa_r));
   printf("%zu\n", offsetof(dg_counters, first_bad));
@@ -70,7 +72,9 @@ int main(void) {
     M, D, C = _abi.Mechanism, _abi.Desc, _abi.Counters
     expect = [ctypes.sizeof(M), ctypes.sizeof(D), ctypes.sizeof(C),
               D.mech.offset, D.gamma.offset, D.newton_tol.offset, D.device.offset, D.patch_hi.offset,
-              D.volume.offset, D.rho_floor.offset, D.p_floor.offset, C.floored.offset, M.nu_f.offset, M.eff.offset, M.kappa_r.offset, C.first_bad.offset]
+              D.volume.offset, D.rho_floor.offset, D.p_floor.offset, C.floored.offset,
+              D.vib.offset, ctypes.sizeof(_abi.Vibration), _abi.Vibration.park_sigma.offset,
+              _abi.Vibration.two_temp.offset, M.nu_f.offset, M.eff.offset, M.kappa_r.offset, C.first_bad.offset]
     assert vals == expect
 
 

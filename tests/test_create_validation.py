@@ -15,7 +15,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(_abi.LIB_PATH), reason="libdg
 
 def desc(dim=3, degree=3, nel=(4, 4, 4), physics=_abi.DG_EULER, precision=_abi.DG_F64, batch=1,
          patch=None, gamma=1.4, mu=0.0, prandtl=0.72, mech=None, volume=_abi.DG_VOLUME_STANDARD,
-         rho_floor=0.0, p_floor=0.0):
+         rho_floor=0.0, p_floor=0.0, vib=None):
     d = _abi.Desc()
     d.dim, d.degree, d.physics, d.precision, d.batch = dim, degree, physics, precision, batch
     for l in range(3):
@@ -34,6 +34,11 @@ def desc(dim=3, degree=3, nel=(4, 4, 4), physics=_abi.DG_EULER, precision=_abi.D
     d.newton_max_iter, d.newton_tol, d.device = 25, 1e-13, 0
     d.volume = volume
     d.rho_floor, d.p_floor = rho_floor, p_floor
+    if vib == "air5":
+        import dginputs as di
+        from paper_2605_26388_amd.solver import vibration_struct
+        d._vib_keep = vibration_struct(di.air5_vibration(di.air5_mechanism(42)))
+        d.vib = ctypes.pointer(d._vib_keep)
     return d
 
 
@@ -69,6 +74,8 @@ def create(d):
     (dict(p_floor=float("inf")), _abi.DG_ERR_ARG, "floor"),
     (dict(physics=_abi.DG_REACTING_EULER, dim=2, nel=(8, 8), rho_floor=1e-6, mech="air5"),
      _abi.DG_ERR_UNSUPPORTED, "floor"),
+    (dict(physics=_abi.DG_REACTING_2T, dim=2, nel=(8, 8), mech="air5"), _abi.DG_ERR_ARG, "vib"),
+    (dict(physics=_abi.DG_REACTING_2T, dim=3, mech="air5", vib="air5"), _abi.DG_ERR_UNSUPPORTED, "2-D"),
 ])
 def test_invalid_descriptors_rejected(kw, code, msg):
     rc, err = create(desc(**kw))
@@ -95,7 +102,8 @@ def test_null_arguments():
 @pytest.mark.parametrize("kw", [dict(), dict(volume=_abi.DG_VOLUME_SPLIT),
                                 dict(dim=2, nel=(8, 8), patch=((2, 2), (4, 4)), volume=_abi.DG_VOLUME_SPLIT,
                                      precision=_abi.DG_F32),
-                                dict(rho_floor=1e-6, p_floor=5e-7)])
+                                dict(rho_floor=1e-6, p_floor=5e-7),
+                                dict(physics=_abi.DG_REACTING_2T, dim=2, nel=(8, 8), mech="air5", vib="air5")])
 def test_valid_descriptor_passes_the_checks(kw):
     rc, err = create(desc(**kw))
     # no device here: the only failure left is the device query itself
