@@ -338,6 +338,37 @@ def bench_ssprk54(steps, warmup):
     return out
 
 
+def bench_reacting_2t(reps):
+    """Two-temperature version of the reacting workload: stage, source mode 0,
+    implicit substep (mode 1) at h = dt/2 and a Strang step, FP64."""
+    from paper_2605_26388_amd import Solver
+    p = di.PRESETS["air5_2t_2d"]
+    mech = di.air5_mechanism(p["mech_seed"])
+    vib = di.air5_vibration(mech)
+    s = Solver(2, 3, p["nel"], p["lo"], p["hi"], physics="reacting_2t", patch_lo=p["patch_lo"],
+               patch_hi=p["patch_hi"], mech=mech, vib=vib)
+    X = s.node_coords().cpu().numpy()
+    U0 = torch.tensor(di.reacting2t_state(X, p["lo"], p["hi"], mech, vib, u0=250.0))[None].to(s.device).contiguous()
+    dt = s.dt_cfl(U0, p["cfl"])
+    nodes = s.E * s.Np
+    U, t1, t2 = U0.clone(), s.empty(), s.empty()
+    restore = lambda: U.copy_(U0)  # noqa: E731
+    stage = time_calls(lambda: s.ssprk3_step(U, dt, t1, t2), reps, reset=restore) / 3
+    out0 = torch.zeros_like(U0)
+    src0 = time_calls(lambda: s.source_chem(U0, out0, 0.0, 0), reps)
+    out1 = s.empty()
+    s.status(reset=True)
+    src1 = time_calls(lambda: s.source_chem(U0, out1, 0.5 * dt, 1), reps)
+    st = s.status()
+    strang = time_calls(lambda: s.strang_step(U, dt, t1, t2), max(2, reps // 4), reset=restore)
+    s.close()
+    return {"workload": "air5_2t_2d: two-temperature reacting Euler 64^2 + 2:1 16^2 patch, N=3, 5-species air, FP64",
+            "stage_ms": stage * 1e3, "source_mode0_node_evals_per_s": nodes / src0,
+            "source_mode1_nodes_per_s": nodes / src1, "source_mode1_ms": src1 * 1e3,
+            "newton_iters_max": st["newton_iters_max"], "newton_unconverged": st["newton_unconverged"],
+            "strang_step_ms": strang * 1e3}
+
+
 def bench_adjoint(steps):
     """Adjoint workload (16^3, N=3, batch 8) in FP32: forward SSP-RK3 step vs
     its reverse sweep with stored stage states."""
@@ -373,7 +404,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--only", choices=["f64", "f32"], default=None,
                     help="time one form only (profiling runs)")
-    ap.add_argument("--side", choices=["adjoint", "navier_stokes", "navier_stokes_L", "reacting", "split", "ssprk54"],
+    ap.add_argument("--side", choices=["adjoint", "navier_stokes", "navier_stokes_L", "reacting", "reacting_2t", "split",
+                                       "ssprk54"],
                     default=None,
                     help="instead: run one side workload alone and print its JSON (profiling runs)")
     ap.add_argument("--calib-copy", type=int, default=0,
@@ -400,6 +432,7 @@ def main():
               "navier_stokes": lambda: bench_navier_stokes(reps),
               "navier_stokes_L": lambda: bench_navier_stokes(reps, nel=(32, 32, 32)),
               "reacting": lambda: bench_reacting(reps),
+              "reacting_2t": lambda: bench_reacting_2t(reps),
               "split": lambda: bench_split(args.steps, args.warmup),
               "ssprk54": lambda: bench_ssprk54(args.steps, args.warmup // 2)}[args.side]
         print(json.dumps({args.side: fn()}), flush=True)
@@ -466,6 +499,8 @@ def main():
         out["navier_stokes"] = bench_navier_stokes(max(5, args.steps // 10))
         log("reacting workload ...")
         out["reacting"] = bench_reacting(max(5, args.steps // 10))
+        log("two-temperature reacting workload ...")
+        out["reacting_2t"] = bench_reacting_2t(max(5, args.steps // 10))
         log("split-form workload ...")
         out["split"] = bench_split(args.steps, args.warmup)
         log("SSPRK54 workload ...")
