@@ -1,0 +1,153 @@
+"""Pins of the oracle's curvilinear operator and boundary fluxes against what
+the mathematics fixes: reduction to the Cartesian operator at zero warp,
+free-stream preservation (the discrete GCL) and conservation on warped
+periodic meshes, the Jacobian against the analytic determinant of the warp
+(spectral convergence and the preserved area), vortex convergence on a warped
+mesh, slip walls (no mass or energy through them; a flow tangent to straight
+walls is steady) and supersonic inflow/outflow (a uniform supersonic stream is
+steady through curved boundaries)."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import dginputs as di
+from oracle.curvilinear import CurvMesh, CurvOperator
+from oracle.dgsem import Operator
+from oracle.mesh import cartesian_mesh
+from oracle.physics import Euler
+from oracle.timestep import ssprk33_step
+
+G = 1.4
+
+
+def weights(m):
+    w = m.w
+    Wt = w
+    for _ in range(m.dim - 1):
+        Wt = Wt.unsqueeze(0) * w.reshape((-1,) + (1,) * Wt.dim())
+    return m.J * Wt[None]
+
+
+def rand_state(m, seed):
+    rng = np.random.default_rng(seed)
+    shape = m.X.shape[1:]
+    rho = rng.uniform(0.5, 1.5, shape)
+    vel = [rng.uniform(-0.5, 0.5, shape) for _ in range(m.dim)]
+    p = rng.uniform(0.5, 1.5, shape)
+    return torch.tensor(di.conserved_from_primitive(rho, vel, p, G))[None]
+
+
+def uniform(m, rho, vel, p):
+    U = torch.zeros((1, m.dim + 2) + tuple(m.X.shape[1:]), dtype=torch.float64)
+    U[:, 0] = rho
+    for d in range(m.dim):
+        U[:, 1 + d] = rho * vel[d]
+    U[:, -1] = p / (G - 1) + 0.5 * rho * sum(v * v for v in vel)
+    return U
+
+
+def flux_scale(m, U):
+    ph = Euler(m.dim)
+    P = ph.prims(U)
+    F = max(float(ph.flux(U, l, P).abs().max()) for l in range(m.dim))
+    Ja = max(float(m.Ja[l].abs().max()) for l in range(m.dim))
+    return F * Ja * float(m.D.abs().sum(1).max()) / float(m.J.abs().min())
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_zero_warp_equals_cartesian_operator(dim):
+    nel, lo, hi = ((4, 3), (0, 0), (1.0, 1.3)) if dim == 2 else ((3, 2, 3), (0, 0, 0), (1.0, 0.8, 1.2))
+    m = CurvMesh(dim, 3, nel, lo, hi, 0.0)
+    U = rand_state(m, 1)
+    a = CurvOperator(m).rhs(U)
+    b = Operator(cartesian_mesh(dim, 3, nel, lo, hi), Euler(dim)).rhs(U)
+    assert float((a - b).abs().max()) < 1e-13 * float(b.abs().max())
+
+
+@pytest.mark.parametrize("dim,N", [(2, 2), (2, 4), (3, 2), (3, 3)])
+def test_free_stream_and_conservation_on_warped_mesh(dim, N):
+    nel = (4, 3) if dim == 2 else (3, 3, 2)
+    lo, hi = (0.0,) * dim, (1.0, 1.2, 0.9)[:dim]
+    m = CurvMesh(dim, N, nel, lo, hi, 0.04)
+    assert float(m.J.min()) > 0
+    op = CurvOperator(m)
+    c = uniform(m, 1.1, (0.3, -0.2, 0.1)[:dim], 0.9)
+    assert float(op.rhs(c).abs().max()) < 1e-13 * flux_scale(m, c)
+    U = rand_state(m, 2)
+    dU = op.rhs(U)
+    wJ = weights(m)
+    red = tuple(range(1, 1 + dim))
+    I = torch.stack([(wJ * dU[0, v]).sum(dim=(0,) + red) for v in range(dim + 2)])
+    S = torch.stack([(wJ * dU[0, v].abs()).sum(dim=(0,) + red) for v in range(dim + 2)])
+    assert float((I.abs() / S).max()) < 1e-13
+
+
+def test_jacobian_against_the_analytic_determinant():
+    """2-D warp: det = 1 - 4 pi^2 A^2 cos(2 pi s_x) cos(2 pi s_y) in physical
+    units; the reference Jacobian is that times (h_x/2)(h_y/2).  The
+    polynomial J converges spectrally and the area is preserved."""
+    A, lo, hi, nel = 0.05, (0.0, 0.0), (1.0, 1.0), (4, 4)
+    errs = []
+    for N in (3, 6):
+        m = CurvMesh(2, N, nel, lo, hi, A)
+        Xc = torch.tensor(m.base.coords())
+        exact = (1 - 4 * math.pi ** 2 * A ** 2 * torch.cos(2 * math.pi * Xc[0]) * torch.cos(2 * math.pi * Xc[1]))
+        exact = exact * (0.25 / 2) ** 2
+        errs.append(float(((m.J - exact) / exact).abs().max()))
+        area = float(weights(m).sum())
+        assert abs(area - 1.0) < (1e-3 if N == 3 else 1e-7)
+    assert errs[1] < errs[0] / 50 and errs[1] < 1e-5, errs
+
+
+def test_vortex_convergence_on_warped_mesh():
+    errs = []
+    for nel in (8, 16):
+        m = CurvMesh(2, 3, (nel, nel), (-5, -5), (5, 5), 0.02)
+        op = CurvOperator(m)
+        U = torch.tensor(di.vortex(m.coords(), 0.0))[None]
+        T = 0.5
+        h = 10.0 / nel
+        dt = 0.5 * h / (7 * op.lam_max(U))
+        nsteps = int(np.ceil(T / dt))
+        dt = T / nsteps
+        for _ in range(nsteps):
+            U = ssprk33_step(op, U, dt)
+        ex = torch.tensor(di.vortex(m.coords(), T))[None]
+        errs.append(float((U[:, 0] - ex[:, 0]).abs().max()))
+    order = math.log2(errs[0] / errs[1])
+    assert 2.8 < order < 5.5, (errs, order)
+
+
+def test_slip_walls_conserve_mass_and_energy():
+    for dim in (2, 3):
+        nel = (4, 3) if dim == 2 else (3, 2, 2)
+        m = CurvMesh(dim, 3, nel, (0.0,) * dim, (1.0, 1.2, 0.9)[:dim], 0.03, bc=("wall",) * (2 * dim))
+        op = CurvOperator(m)
+        U = rand_state(m, 3)
+        dU = op.rhs(U)
+        wJ = weights(m)
+        red = tuple(range(0, 1 + dim))
+        for v in (0, dim + 1):
+            assert abs(float((wJ * dU[0, v]).sum())) < 1e-13 * float((wJ * dU[0, v].abs()).sum())
+        mom = abs(float((wJ * dU[0, 1]).sum())) / float((wJ * dU[0, 1].abs()).sum())
+        assert mom > 1e-6          # walls push: momentum is not conserved
+
+
+def test_flow_tangent_to_straight_walls_is_steady():
+    m = CurvMesh(2, 3, (4, 3), (0.0, 0.0), (1.0, 1.0), 0.0, bc=("periodic", "periodic", "wall", "wall"))
+    c = uniform(m, 1.2, (0.7, 0.0), 1.1)
+    assert float(CurvOperator(m).rhs(c).abs().max()) < 1e-13 * flux_scale(m, c)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_uniform_supersonic_stream_through_curved_boundaries(dim):
+    nel = (4, 3) if dim == 2 else (3, 2, 2)
+    bc = ("inflow", "outflow") + ("periodic", "periodic") * (dim - 1)
+    m = CurvMesh(dim, 3, nel, (0.0,) * dim, (1.0, 1.0, 1.0)[:dim], 0.03, bc=bc)
+    vel = (2.5, 0.3, -0.2)[:dim]                # Mach > 2 along x
+    c = uniform(m, 1.0, vel, 1.0 / G)
+    op = CurvOperator(m, bc_state=c[0, :, 0].reshape(dim + 2, -1)[:, 0].numpy())
+    assert float(op.rhs(c).abs().max()) < 1e-13 * flux_scale(m, c)
