@@ -78,6 +78,12 @@ enum dg_precision { DG_F64 = 0, DG_F32 = 1 };
  *   physics only; the interface flux stays Rusanov; no adjoint. */
 enum dg_volume { DG_VOLUME_STANDARD = 0, DG_VOLUME_SPLIT = 1 };
 
+/* Box-side boundary types.  DG_BC_WALL: slip wall, the Rusanov flux against
+ * the mirrored state (rho, m - 2 (m.n) n, E) (no mass or energy through it).
+ * DG_BC_INFLOW: supersonic inflow, the exact flux of dg_desc.bc_state.
+ * DG_BC_OUTFLOW: supersonic outflow, the exact flux of the interior state. */
+enum dg_bc { DG_BC_PERIODIC = 0, DG_BC_WALL = 1, DG_BC_INFLOW = 2, DG_BC_OUTFLOW = 3 };
+
 /* Reaction mechanism (Source Terms section; finite-rate appendix).
  * Species data per unit mass (SI); rate constants k = A T^beta exp(-Theta/T)
  * in the units implied by kappa_c: concentrations [X_s] = kappa_c rho_s/W_s,
@@ -147,6 +153,22 @@ typedef struct dg_desc {
    * it off; Euler and Navier-Stokes physics only. */
   double rho_floor, p_floor;
   const dg_vibration* vib; /* DG_REACTING_2T only; NULL otherwise */
+  /* Curvilinear elements and boundary fluxes (Kernel Architecture for
+   * Hyperbolic Terms: element map x = X(xi), per-node J and Ja^l with the
+   * discrete GCL; boundary fluxes per type).  warp != 0 moves every node of
+   * the box by the smooth map
+   *   2-D: x~ = x + warp L_x sin(2 pi s_y),  y~ = y + warp L_y sin(2 pi s_x),
+   *   3-D: x~_d = x_d + warp L_d sin(2 pi s_{d+1}) sin(2 pi s_{d+2}),
+   * s_d = (x_d - lo_d)/L_d; the element geometry is the degree-N interpolant
+   * of its nodes, metrics come from it (cross-product form in 2-D, conservative
+   * curl form in 3-D).  bc[2l] / bc[2l+1] is the type of the lo / hi side of
+   * direction l (dg_bc; both periodic or neither); bc_state is the conserved
+   * state of inflow sides.  Curvilinear meshes (warp != 0 or a non-periodic
+   * side): Euler physics, FP64, standard volume integral, no refined patch, no
+   * adjoint; the mesh must not fold (J > 0 at every node). */
+  double warp;
+  int32_t bc[6];
+  double bc_state[5];
 } dg_desc;
 
 /* Sticky device-side counters (dg_status_read). */

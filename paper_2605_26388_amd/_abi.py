@@ -18,6 +18,7 @@ DG_OK, DG_ERR_ARG, DG_ERR_UNSUPPORTED, DG_ERR_HIP, DG_ERR_OOM, DG_ERR_NONPHYSICA
 DG_EULER, DG_NAVIER_STOKES, DG_REACTING_EULER, DG_REACTING_2T = range(4)
 DG_F64, DG_F32 = range(2)
 DG_VOLUME_STANDARD, DG_VOLUME_SPLIT = range(2)
+DG_BC_PERIODIC, DG_BC_WALL, DG_BC_INFLOW, DG_BC_OUTFLOW = range(4)
 
 EXPORTS = (
     "dg_create", "dg_destroy", "dg_sizes", "dg_node_coords", "dg_rhs", "dg_rk_stage", "dg_rk_stage_dual",
@@ -65,6 +66,7 @@ class Desc(ctypes.Structure):
         ("volume", c_int32),
         ("rho_floor", c_double), ("p_floor", c_double),
         ("vib", POINTER(Vibration)),
+        ("warp", c_double), ("bc", c_int32 * 6), ("bc_state", c_double * 5),
     ]
 
 

@@ -294,6 +294,11 @@ int build_mesh(const dg_desc& d, MeshBuild& mb) {
         if (lev[e] == 0) {
           int c[3] = {cxs[e], cys[e], czs[e]};
           c[l] += sgn;
+          if (d.bc[2 * l] != DG_BC_PERIODIC && (c[l] < 0 || c[l] >= nel[l])) {
+            // box side without periodicity: boundary face, code -(1 + type)
+            *slot = -(1 + d.bc[2 * l + side]);
+            continue;
+          }
           const int nb = cid(c[0], c[1], c[2]);
           if (nb >= 0) {
             *slot = nb;
@@ -339,6 +344,101 @@ int build_mesh(const dg_desc& d, MeshBuild& mb) {
   return DG_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Curvilinear geometry: warped node coordinates and per-node metrics from the
+// degree-N interpolant of every element's nodes (the collocation derivative
+// D applied to the node coordinates).  2-D: Ja^1 = (y_2, -x_2),
+// Ja^2 = (-y_1, x_1); 3-D: conservative curl form
+// (Ja^i)_n = -[curl_xi (X_l grad_xi X_m)]_i with (n, m, l) cyclic, the
+// products formed node by node.  J = det(dX_d/dxi_m).  Returns false if the
+// map folds (J <= 0 somewhere).
+// ---------------------------------------------------------------------------
+static void warp_point(const dg_desc& d, const double* x, double* y) {
+  const double kTwoPi = 6.283185307179586;
+  double L[3], s[3];
+  for (int q = 0; q < d.dim; ++q) {
+    L[q] = d.hi[q] - d.lo[q];
+    s[q] = (x[q] - d.lo[q]) / L[q];
+  }
+  if (d.dim == 2) {
+    y[0] = x[0] + d.warp * L[0] * std::sin(kTwoPi * s[1]);
+    y[1] = x[1] + d.warp * L[1] * std::sin(kTwoPi * s[0]);
+  } else {
+    for (int q = 0; q < 3; ++q)
+      y[q] = x[q] + d.warp * L[q] * std::sin(kTwoPi * s[(q + 1) % 3]) * std::sin(kTwoPi * s[(q + 2) % 3]);
+  }
+}
+
+static bool build_curv(const dg_desc& d, const Ctx& c, const MeshBuild& mb, std::vector<double>& met,
+                       std::vector<double>& xyz) {
+  const int dim = c.dim, n = c.n, NP = c.Np, E = c.E;
+  const size_t P = (size_t)E * NP;
+  met.assign((size_t)(2 + dim * dim) * P, 0.0);
+  xyz.assign((size_t)dim * P, 0.0);
+  const double* D = c.h_K.D;
+  const int stride[3] = {1, n, n * n};
+  std::vector<double> X(3 * NP), dX(9 * NP), V(3 * NP);
+  auto ijk = [&](int node, int m) { return (node / stride[m]) % n; };
+  // d f / d xi_m at `node` for a nodal field f of one element
+  auto deriv = [&](const double* f, int m, int node) {
+    const int i = ijk(node, m);
+    const int base = node - i * stride[m];
+    double acc = 0.0;
+    for (int k = 0; k < n; ++k) acc += D[i * n + k] * f[base + k * stride[m]];
+    return acc;
+  };
+  for (int e = 0; e < E; ++e) {
+    for (int node = 0; node < NP; ++node) {
+      double xc[3] = {0.0, 0.0, 0.0}, xw[3] = {0.0, 0.0, 0.0};
+      for (int q = 0; q < dim; ++q) {
+        const double h = 2.0 / mb.geo[(size_t)e * 4 + q];
+        xc[q] = mb.corner[(size_t)e * 3 + q] + (c.h_K.xi[ijk(node, q)] + 1.0) * 0.5 * h;
+      }
+      warp_point(d, xc, xw);
+      for (int q = 0; q < dim; ++q) X[q * NP + node] = xw[q];
+    }
+    for (int q = 0; q < dim; ++q)
+      for (int m = 0; m < dim; ++m)
+        for (int node = 0; node < NP; ++node) dX[(q * 3 + m) * NP + node] = deriv(&X[q * NP], m, node);
+    for (int node = 0; node < NP; ++node) {
+      double Ja[3][3] = {{0.0}}, J;
+      auto dx = [&](int q, int m) { return dX[(q * 3 + m) * NP + node]; };
+      if (dim == 2) {
+        Ja[0][0] = dx(1, 1);
+        Ja[0][1] = -dx(0, 1);
+        Ja[1][0] = -dx(1, 0);
+        Ja[1][1] = dx(0, 0);
+        J = dx(0, 0) * dx(1, 1) - dx(0, 1) * dx(1, 0);
+      } else {
+        J = dx(0, 0) * (dx(1, 1) * dx(2, 2) - dx(1, 2) * dx(2, 1)) - dx(0, 1) * (dx(1, 0) * dx(2, 2) - dx(1, 2) * dx(2, 0)) +
+            dx(0, 2) * (dx(1, 0) * dx(2, 1) - dx(1, 1) * dx(2, 0));
+      }
+      if (!(J > 0.0)) return false;
+      const size_t at = (size_t)e * NP + node;
+      met[at] = J;
+      met[P + at] = 1.0 / J;
+      if (dim == 2)
+        for (int l = 0; l < 2; ++l)
+          for (int q = 0; q < 2; ++q) met[(2 + l * 2 + q) * P + at] = Ja[l][q];
+      for (int q = 0; q < dim; ++q) xyz[q * P + at] = X[q * NP + node];
+    }
+    if (dim == 3) {
+      for (int nn = 0; nn < 3; ++nn) {
+        const int mm = (nn + 1) % 3, ll = (nn + 2) % 3;
+        for (int k = 0; k < 3; ++k)
+          for (int node = 0; node < NP; ++node) V[k * NP + node] = X[ll * NP + node] * dX[(mm * 3 + k) * NP + node];
+        for (int node = 0; node < NP; ++node)
+          for (int i = 0; i < 3; ++i) {
+            const double curl = deriv(&V[((i + 2) % 3) * NP], (i + 1) % 3, node) -
+                                deriv(&V[((i + 1) % 3) * NP], (i + 2) % 3, node);
+            met[(2 + i * 3 + nn) * P + (size_t)e * NP + node] = -curl;
+          }
+      }
+    }
+  }
+  return true;
+}
+
 bool overlaps(const void* a, const void* b, size_t bytes) {
   if (!a || !b) return false;
   const char* pa = static_cast<const char*>(a);
@@ -377,7 +477,8 @@ __global__ void k_reset_counters(int* cnt, unsigned long long* first_bad) {
 
 void free_ctx(Ctx& c) {
   void* ptrs[] = {c.d_nbr, c.d_geo, c.d_K, c.d_counters, c.d_first_bad, c.d_mortars,
-                  c.d_mortar_flux, c.d_red, c.d_red_out, c.d_face, c.d_mech, c.d_vib, c.d_corner};
+                  c.d_mortar_flux, c.d_red, c.d_red_out, c.d_face, c.d_mech, c.d_vib, c.d_corner,
+                  c.d_met, c.d_xyz};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -465,6 +566,31 @@ int dg_create(const dg_desc* desc, dg_ctx** out) {
       break;
     default: return fail(DG_ERR_ARG, "unknown physics");
   }
+  bool curv = d.warp != 0.0;
+  if (!std::isfinite(d.warp) || !(std::fabs(d.warp) < 0.25)) return fail(DG_ERR_ARG, "warp must be finite, |warp| < 0.25");
+  for (int l = 0; l < d.dim; ++l) {
+    const int a = d.bc[2 * l], b = d.bc[2 * l + 1];
+    if (a < DG_BC_PERIODIC || a > DG_BC_OUTFLOW || b < DG_BC_PERIODIC || b > DG_BC_OUTFLOW)
+      return fail(DG_ERR_ARG, "bc must hold dg_bc values");
+    if ((a == DG_BC_PERIODIC) != (b == DG_BC_PERIODIC))
+      return fail(DG_ERR_ARG, "bc: a direction is periodic on both sides or on neither");
+    if (a != DG_BC_PERIODIC) curv = true;
+  }
+  if (curv) {
+    if (d.physics != DG_EULER) return fail(DG_ERR_UNSUPPORTED, "curvilinear meshes and boundaries: Euler physics only");
+    if (patch) return fail(DG_ERR_UNSUPPORTED, "curvilinear meshes and boundaries: no refined patch");
+    if (d.volume != DG_VOLUME_STANDARD)
+      return fail(DG_ERR_UNSUPPORTED, "curvilinear meshes and boundaries: standard volume integral only");
+    if (d.precision != DG_F64) return fail(DG_ERR_UNSUPPORTED, "curvilinear meshes and boundaries: FP64 only");
+    bool inflow = false;
+    for (int q = 0; q < 2 * d.dim; ++q) inflow = inflow || d.bc[q] == DG_BC_INFLOW;
+    if (inflow) {
+      double m2 = 0.0;
+      for (int q = 0; q < d.dim; ++q) m2 += d.bc_state[1 + q] * d.bc_state[1 + q];
+      const double p = (d.gamma - 1.0) * (d.bc_state[d.dim + 1] - 0.5 * m2 / d.bc_state[0]);
+      if (!(d.bc_state[0] > 0.0) || !(p > 0.0)) return fail(DG_ERR_ARG, "bc_state must have rho > 0 and p > 0");
+    }
+  }
   if (!(d.rho_floor >= 0.0) || !(d.p_floor >= 0.0) || !std::isfinite(d.rho_floor) || !std::isfinite(d.p_floor))
     return fail(DG_ERR_ARG, "rho_floor and p_floor must be finite and >= 0");
   if ((d.rho_floor > 0.0 || d.p_floor > 0.0) && is_reacting(d.physics))
@@ -519,6 +645,12 @@ int dg_create(const dg_desc* desc, dg_ctx** out) {
   c.h_corner = mb.corner;
   c.h_geo = mb.geo;
   build_refconsts(c.N, c.h_K);
+  c.curv = curv;
+  std::vector<double> met, xyz;
+  if (curv && !build_curv(d, c, mb, met, xyz)) {
+    delete ctx;
+    return fail(DG_ERR_ARG, "warp folds the mesh (J <= 0 at some node)");
+  }
 
   DeviceGuard guard(c.device);
   hipError_t e = hipSuccess;
@@ -551,6 +683,14 @@ int dg_create(const dg_desc* desc, dg_ctx** out) {
       free_ctx(c);
       delete ctx;
       return hip_fail(e, "dg_create mechanism");
+    }
+  }
+  if (curv) {
+    if ((e = upload(&c.d_met, met.data(), met.size() * sizeof(double))) != hipSuccess ||
+        (e = upload(&c.d_xyz, xyz.data(), xyz.size() * sizeof(double))) != hipSuccess) {
+      free_ctx(c);
+      delete ctx;
+      return hip_fail(e, "dg_create metrics");
     }
   }
   if (d.physics == DG_NAVIER_STOKES) {
@@ -594,7 +734,12 @@ int dg_node_coords(const dg_ctx* ctx, double* xyz, void* stream) {
   if (!ctx || !xyz) return fail(DG_ERR_ARG, "dg_node_coords: null argument");
   const Ctx& c = ctx->c;
   DeviceGuard guard(c.device);
-  hipError_t e = launch_coords(c, c.d_corner, xyz, static_cast<hipStream_t>(stream));
+  hipError_t e;
+  if (c.curv)
+    e = hipMemcpyAsync(xyz, c.d_xyz, (size_t)c.dim * c.E * c.Np * sizeof(double), hipMemcpyDeviceToDevice,
+                       static_cast<hipStream_t>(stream));
+  else
+    e = launch_coords(c, c.d_corner, xyz, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? DG_OK : hip_fail(e, "dg_node_coords");
 }
 
@@ -626,6 +771,8 @@ static int run_stage(dg_ctx* ctx, const void* U0, const void* Uk, void* out, dou
   hipError_t e;
   if (c.desc.physics == DG_NAVIER_STOKES) {
     e = launch_ns(c, sp, s);
+  } else if (c.curv) {
+    e = launch_curv(c, sp, s);
   } else {
     e = launch_mortar(c, Uk, s);
     if (e == hipSuccess) e = launch_stage(c, sp, s);
@@ -715,6 +862,7 @@ int dg_rhs_adjoint(dg_ctx* ctx, const void* U, const void* lam_L, void* lam_U, v
     return fail(DG_ERR_UNSUPPORTED, "adjoint: Euler physics on conforming meshes, degree <= 4");
   if (c.desc.volume != DG_VOLUME_STANDARD)
     return fail(DG_ERR_UNSUPPORTED, "adjoint: standard volume integral only");
+  if (c.curv) return fail(DG_ERR_UNSUPPORTED, "adjoint: Cartesian periodic meshes only");
   const size_t bytes = state_bytes(c);
   if (overlaps(lam_U, U, bytes) || overlaps(lam_U, lam_L, bytes))
     return fail(DG_ERR_ARG, "dg_rhs_adjoint: lam_U aliases an input");
@@ -731,6 +879,7 @@ int dg_rk_stage_adjoint(dg_ctx* ctx, const void* Uk, const void* lam_out, void* 
     return fail(DG_ERR_UNSUPPORTED, "adjoint: Euler physics on conforming meshes, degree <= 4");
   if (c.desc.volume != DG_VOLUME_STANDARD)
     return fail(DG_ERR_UNSUPPORTED, "adjoint: standard volume integral only");
+  if (c.curv) return fail(DG_ERR_UNSUPPORTED, "adjoint: Cartesian periodic meshes only");
   if (lam0_mode != DG_LAM0_ACCUMULATE && lam0_mode != DG_LAM0_FOLD && lam0_mode != DG_LAM0_INIT)
     return fail(DG_ERR_ARG, "dg_rk_stage_adjoint: unknown lam0_mode");
   const size_t bytes = state_bytes(c);

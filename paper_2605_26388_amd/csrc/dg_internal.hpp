@@ -97,6 +97,11 @@ struct Ctx {
   void* d_face = nullptr;        // BR1 face buffer
   void* d_mech = nullptr;        // mechanism copy on device
   void* d_vib = nullptr;         // vibrational data on device (two-temperature)
+  // curvilinear meshes: metric planes [2 + dim*dim][E*Np] (J, 1/J, Ja^l_d at
+  // plane 2 + l*dim + d) and the warped node coordinates [dim][E*Np]
+  bool curv = false;
+  double* d_met = nullptr;
+  double* d_xyz = nullptr;
   std::vector<double> h_corner;  // host copy [E][3] lower corners (coords)
   std::vector<double> h_geo;     // host copy [E][4]
 };
@@ -113,6 +118,7 @@ hipError_t launch_integrals(const Ctx& c, const void* U, double* d_out, hipStrea
 hipError_t launch_lam_max(const Ctx& c, const void* U, double* d_out, hipStream_t s);
 hipError_t launch_source(const Ctx& c, const void* U, void* out, double h, int mode, hipStream_t s);
 hipError_t launch_ns(const Ctx& c, const StageParams& sp, hipStream_t s);
+hipError_t launch_curv(const Ctx& c, const StageParams& sp, hipStream_t s);
 hipError_t launch_adjoint(const Ctx& c, const void* U, const void* lam_out, void* lam_k, void* lam_0,
                           double a, double b, double cdt, int accumulate, hipStream_t s);
 

@@ -58,7 +58,7 @@ __device__ void block_sum(double (&x)[NQ], double (*sh)[NQ]) {
 // Grid (RED_BLOCKS, B); block j covers a contiguous node range.
 template <typename T>
 __global__ void __launch_bounds__(RED_BS)
-k_integrals(const T* U, int dim, int n, int E, int nv, int nspec, const double* geo,
+k_integrals(const T* U, int dim, int n, int E, int nv, int nspec, const double* geo, const double* jnode,
             const RefConsts* K, double* partial) {
   __shared__ double sh[RED_BS / 64][RED_MAXQ];
   const int b = blockIdx.y;
@@ -74,7 +74,8 @@ k_integrals(const T* U, int dim, int n, int E, int nv, int nspec, const double* 
   for (size_t t = t0 + threadIdx.x; t < t1; t += RED_BS) {
     const int e = (int)(t / Np);
     const int node = (int)(t - (size_t)e * Np);
-    double wt = geo[(size_t)e * 4 + 3] * K->w[node % n] * K->w[(node / n) % n];
+    // Jacobian per element (affine) or per node (curvilinear)
+    double wt = (jnode ? jnode[t] : geo[(size_t)e * 4 + 3]) * K->w[node % n] * K->w[(node / n) % n];
     if (dim == 3) wt *= K->w[node / (n * n)];
     double rho = 0.0, m2 = 0.0;
     for (int v = 0; v < nv; ++v) {
@@ -108,10 +109,10 @@ hipError_t launch_integrals(const Ctx& c, const void* U, double* d_out, hipStrea
   dim3 grid(RED_BLOCKS, c.B);
   if (c.desc.precision == DG_F32)
     hipLaunchKernelGGL((k_integrals<float>), grid, dim3(RED_BS), 0, s, static_cast<const float*>(U), c.dim, c.n,
-                       c.E, c.nv, nspec, c.d_geo, c.d_K, c.d_red);
+                       c.E, c.nv, nspec, c.d_geo, c.curv ? c.d_met : nullptr, c.d_K, c.d_red);
   else
     hipLaunchKernelGGL((k_integrals<double>), grid, dim3(RED_BS), 0, s, static_cast<const double*>(U), c.dim, c.n,
-                       c.E, c.nv, nspec, c.d_geo, c.d_K, c.d_red);
+                       c.E, c.nv, nspec, c.d_geo, c.curv ? c.d_met : nullptr, c.d_K, c.d_red);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_final_sum, dim3(c.B), dim3(RED_BS), 0, s, c.d_red, RED_BLOCKS, c.nv + 1, d_out);

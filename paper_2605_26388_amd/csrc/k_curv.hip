@@ -1,0 +1,307 @@
+// Fused DGSEM stage for the Euler equations on curvilinear elements with
+// boundary fluxes (Kernel Architecture for Hyperbolic Terms: element map
+// x = X(xi), per-node Jacobian J and contravariant vectors Ja^l satisfying the
+// discrete GCL, contravariant fluxes Ja^l . F; boundary fluxes per type).
+//
+// One lane per node, EPB elements per workgroup, as the Cartesian stage:
+//   1. load U_k, the node's 1/J and Ja^l (metric planes, coalesced);
+//   2. volume integral: contravariant fluxes Ft^l = Ja^l . F (written as
+//      rho v_n, m v_n + p n, (E + p) v_n with n = Ja^l) staged through LDS and
+//      swept with D, -sum_l sum_m D_im Ft^l_m;
+//   3. faces: a lane on the +-xi_l face takes the normal n = Ja^l of its own
+//      node and applies the Rusanov flux as a difference to its own
+//      contravariant flux,
+//         2 (F* - Ft_own) = (Ft_nb - Ft_own) - s lam |n| (U_nb - U_own),
+//         lam = max(|v_own . n^| + a_own, |v_nb . n^| + a_nb),
+//      s = +1 on the +xi_l face, -1 on the -xi_l face, with U_nb the
+//      neighbour's matching node or, on a box side, the boundary state: the
+//      mirrored state (rho, m - 2 (m . n^) n^, E) for a slip wall; a
+//      supersonic inflow takes F* = n . F(U_bc) and a supersonic outflow
+//      F* = Ft_own (no correction);
+//   4. dU = (volume + lift) / J, or the stage combination (positivity floor
+//      and dual output as the Cartesian stage).
+#include <type_traits>
+
+#include "dg_device.hpp"
+
+namespace dg {
+
+struct CurvArgs {
+  const double* met;  // [2 + dim*dim][E*Np]: J, 1/J, Ja^l_d at plane 2 + l*dim + d
+  double ub[5];       // conserved inflow state
+};
+
+// n . F(U) for the Euler flux: (rho v_n, m v_n + p n, (E + p) v_n), v_n = v . n
+template <int DIM>
+__device__ __forceinline__ void normal_flux(const double (&U)[DIM + 2], const double (&vel)[DIM], double p,
+                                            const double (&n)[DIM], double (&F)[DIM + 2]) {
+  double vn = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) vn = fma(vel[d], n[d], vn);
+  F[0] = U[0] * vn;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) F[1 + d] = fma(U[1 + d], vn, p * n[d]);
+  F[DIM + 1] = (U[DIM + 1] + p) * vn;
+}
+
+template <int DIM, int N>
+__global__ void __launch_bounds__((Shape<DIM, N>::BS)) __attribute__((amdgpu_waves_per_eu(3)))
+k_stage_curv(StageParams sp, MeshView mv, PhysConst pc, CurvArgs ca) {
+  using S = Shape<DIM, N>;
+  using PHYS = EulerPhys<DIM>;
+  constexpr int n = S::n, NP = S::NP, EPB = S::EPB, NV = DIM + 2;
+  constexpr bool UNIFORM_ELEM = (NP % 64) == 0;
+
+  __shared__ double sF[DIM][NV][EPB * NP];
+  __shared__ double sD[n * n];
+
+  const int tid = threadIdx.x;
+  static_assert(n * n <= S::BS, "one D entry per lane");
+  const double dval = tid < n * n ? mv.K->D[tid] : 0.0;
+
+  const int E = mv.E;
+  const int nEB = (E + EPB - 1) / EPB;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = blk / nEB;
+  const int eb = blk - b * nEB;
+  const int el = tid / NP;
+  const int node = tid - el * NP;
+  const int e = eb * EPB + el;
+  const bool active = (tid < S::NT) && (e < E);
+  int ec = active ? e : 0;  // clamped for address arithmetic only
+  if constexpr (UNIFORM_ELEM) ec = wave_uniform(ec);
+
+  const int* nb = mv.nbr + (size_t)ec * 2 * DIM;
+  int nbl[2 * DIM];
+#pragma unroll
+  for (int q = 0; q < 2 * DIM; ++q) nbl[q] = nb[q];
+  const double hwinv = 0.5 * mv.K->wend_inv;
+
+  int ii[3];
+  ii[0] = node % n;
+  ii[1] = (node / n) % n;
+  ii[2] = node / (n * n);
+  const int stride[3] = {1, n, n * n};
+
+  const size_t plane = (size_t)E * NP;
+  const size_t abytes = (size_t)NV * plane * sizeof(double);
+  const unsigned pstride = (unsigned)(plane * sizeof(double));
+  const rsrc_t rU = make_rsrc(static_cast<const double*>(sp.Uk) + (size_t)b * NV * plane, abytes);
+  const unsigned off = (unsigned)(ec * NP + node);
+
+  double u[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u[v] = Buf<double>::load(rU, off, v * pstride);
+  // metrics of the own node (shared by all batch members)
+  const size_t at = (size_t)ec * NP + node;
+  const double jinv = ca.met[plane + at];
+  double Ja[DIM][DIM];
+#pragma unroll
+  for (int l = 0; l < DIM; ++l)
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) Ja[l][d] = ca.met[(2 + l * DIM + d) * plane + at];
+
+  // neighbour's matching node on conforming faces (lanes on a face only)
+  int side[DIM];
+  double un[DIM][NV];
+#pragma unroll
+  for (int l = 0; l < DIM; ++l) {
+    side[l] = (ii[l] == 0) ? 0 : ((ii[l] == N) ? 1 : -1);
+    const int ne = side[l] >= 0 ? nbl[2 * l + side[l]] : -1;
+    if (ne >= 0) {
+      const int shift = side[l] == 1 ? -N : N;
+      const unsigned noff = (unsigned)(ne * NP + node + shift * stride[l]);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) un[l][v] = Buf<double>::load(rU, noff, v * pstride);
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) un[l][v] = u[v];
+    }
+  }
+  const bool use_u0 = (sp.mode != 0) && (sp.a != 0.0);
+  double u0[NV];
+  if (use_u0) {
+    const rsrc_t r0 = make_rsrc(static_cast<const double*>(sp.U0) + (size_t)b * NV * plane, abytes);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u0[v] = Buf<double>::load(r0, off, v * pstride);
+  } else {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u0[v] = 0.0;
+  }
+
+  Thermo th;
+  const bool ok = PHYS::thermo(u, th, pc);
+  if (active && !ok)
+    report_nonphysical(mv.counters, mv.first_bad, ((unsigned long long)b * E + e) * NP + node);
+  double vel[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) vel[d] = u[1 + d] * th.ri;
+
+  // ---- contravariant fluxes in LDS -----------------------------------------
+  if (tid < n * n) sD[tid] = dval;
+  if (tid < S::NT) {
+#pragma unroll
+    for (int l = 0; l < DIM; ++l) {
+      double F[NV];
+      normal_flux<DIM>(u, vel, th.p, Ja[l], F);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sF[l][v][tid] = F[v];
+    }
+  }
+  __syncthreads();
+
+  // ---- volume integral: -sum_l sum_m D_im Ft^l_m ----------------------------
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  if (tid < S::NT) {
+#pragma unroll
+    for (int l = 0; l < DIM; ++l) {
+      const int il = ii[l];
+      const int st = stride[l];
+      const int base = tid - il * st;
+      double drow[n];
+#pragma unroll
+      for (int m = 0; m < n; ++m) drow[m] = sD[il * n + m];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m < n; ++m) s = fma(drow[m], sF[l][v][base + m * st], s);
+        acc[v] -= s;
+      }
+    }
+  }
+
+  // ---- surface lift ----------------------------------------------------------
+  const double aown = sound<PHYS>(th);
+#pragma unroll
+  for (int l = 0; l < DIM; ++l) {
+    if (side[l] < 0) continue;  // lanes not on a face in direction l
+    const int code = nbl[2 * l + side[l]];
+    if (code == -(1 + DG_BC_OUTFLOW)) continue;  // F* = own flux
+    double Fo[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fo[v] = sF[l][v][tid < S::NT ? tid : 0];
+    double nrm2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) nrm2 = fma(Ja[l][d], Ja[l][d], nrm2);
+    const double nmag = fsqrt(nrm2);
+    const double nmi = frcp(nmag);
+    double Dv[NV];
+    if (code == -(1 + DG_BC_INFLOW)) {
+      double ub[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) ub[v] = ca.ub[v];
+      Thermo tb;
+      PHYS::thermo(ub, tb, pc);
+      double vb[DIM], Fb[NV];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) vb[d] = ub[1 + d] * tb.ri;
+      normal_flux<DIM>(ub, vb, tb.p, Ja[l], Fb);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Dv[v] = 2.0 * (Fb[v] - Fo[v]);
+    } else {
+      double ug[NV];
+      if (code >= 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) ug[v] = un[l][v];
+      } else {  // slip wall: mirrored state
+        double mn = 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) mn = fma(u[1 + d], Ja[l][d], mn);
+        mn *= nmi;
+        ug[0] = u[0];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) ug[1 + d] = fma(-2.0 * mn, Ja[l][d] * nmi, u[1 + d]);
+        ug[DIM + 1] = u[DIM + 1];
+      }
+      Thermo tn;
+      PHYS::thermo(ug, tn, pc);
+      double vn[DIM], Fn[NV];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) vn[d] = ug[1 + d] * tn.ri;
+      normal_flux<DIM>(ug, vn, tn.p, Ja[l], Fn);
+      double vo = 0.0, vg = 0.0;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        vo = fma(vel[d], Ja[l][d], vo);
+        vg = fma(vn[d], Ja[l][d], vg);
+      }
+      const double co = fabs(vo) * nmi + aown;
+      const double cg = fabs(vg) * nmi + sound<PHYS>(tn);
+      const double lam = co >= cg ? co : cg;
+      const double hs = (side[l] == 1 ? lam : -lam) * nmag;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Dv[v] = fma(-hs, ug[v] - u[v], Fn[v] - Fo[v]);
+    }
+    const double sc = side[l] == 1 ? -hwinv : hwinv;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = fma(sc, Dv[v], acc[v]);
+  }
+
+  // ---- output ----------------------------------------------------------------
+  if (active) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] *= jinv;
+    const rsrc_t ro = make_rsrc(static_cast<double*>(sp.out) + (size_t)b * NV * plane, abytes);
+    if (sp.mode == 0) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Buf<double>::store(ro, off, acc[v], v * pstride);
+    } else {
+      double r[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        r[v] = fma(sp.c, acc[v], sp.b * u[v]);
+        if (use_u0) r[v] = fma(sp.a, u0[v], r[v]);
+      }
+      if (sp.rho_min > 0.0 || sp.p_min > 0.0)
+        positivity_floor(r, sp.rho_min, sp.p_min, 1.0 / (pc.gamma - 1.0), mv.counters);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Buf<double>::store(ro, off, r[v], v * pstride);
+      if (sp.mode == 2) {  // second combination of the same L(Uk), no floor
+        const rsrc_t r2 = make_rsrc(static_cast<double*>(sp.out2) + (size_t)b * NV * plane, abytes);
+        const bool use_v = sp.a2 != 0.0;
+        const rsrc_t rv = make_rsrc(static_cast<const double*>(use_v ? sp.V : sp.Uk) + (size_t)b * NV * plane, abytes);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          double w = fma(sp.c2, acc[v], sp.b2 * u[v]);
+          if (use_v) w = fma(sp.a2, Buf<double>::load(rv, off, v * pstride), w);
+          Buf<double>::store(r2, off, w, v * pstride);
+        }
+      }
+    }
+  }
+}
+
+template <int DIM, int N>
+static hipError_t go_curv(const Ctx& c, const StageParams& sp, const CurvArgs& ca, hipStream_t s) {
+  using SH = Shape<DIM, N>;
+  const int nEB = (c.E + SH::EPB - 1) / SH::EPB;
+  hipLaunchKernelGGL((k_stage_curv<DIM, N>), dim3(nEB * c.B), dim3(SH::BS), 0, s, sp, mesh_view(c), c.pc, ca);
+  return hipGetLastError();
+}
+
+template <int DIM>
+static hipError_t curv_n(const Ctx& c, const StageParams& sp, const CurvArgs& ca, hipStream_t s) {
+  switch (c.N) {
+    case 1: return go_curv<DIM, 1>(c, sp, ca, s);
+    case 2: return go_curv<DIM, 2>(c, sp, ca, s);
+    case 3: return go_curv<DIM, 3>(c, sp, ca, s);
+    case 4: return go_curv<DIM, 4>(c, sp, ca, s);
+    case 5: return go_curv<DIM, 5>(c, sp, ca, s);
+    case 6: return go_curv<DIM, 6>(c, sp, ca, s);
+    case 7: return go_curv<DIM, 7>(c, sp, ca, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_curv(const Ctx& c, const StageParams& sp, hipStream_t s) {
+  if (c.desc.precision != DG_F64 || c.desc.physics != DG_EULER) return hipErrorInvalidValue;
+  CurvArgs ca;
+  ca.met = c.d_met;
+  for (int v = 0; v < 5; ++v) ca.ub[v] = c.desc.bc_state[v];
+  return c.dim == 2 ? curv_n<2>(c, sp, ca, s) : curv_n<3>(c, sp, ca, s);
+}
+
+}  // namespace dg

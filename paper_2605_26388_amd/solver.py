@@ -17,6 +17,8 @@ PHYSICS = {"euler": _abi.DG_EULER, "navier_stokes": _abi.DG_NAVIER_STOKES, "reac
            "reacting_2t": _abi.DG_REACTING_2T}
 PRECISION = {"f64": _abi.DG_F64, "f32": _abi.DG_F32}
 VOLUME = {"standard": _abi.DG_VOLUME_STANDARD, "split": _abi.DG_VOLUME_SPLIT}
+BC = {"periodic": _abi.DG_BC_PERIODIC, "wall": _abi.DG_BC_WALL, "inflow": _abi.DG_BC_INFLOW,
+      "outflow": _abi.DG_BC_OUTFLOW}
 
 
 def mechanism_struct(mech):
@@ -65,7 +67,7 @@ class Solver:
     def __init__(self, dim, degree, nel, lo, hi, physics="euler", precision="f64", batch=1,
                  patch_lo=None, patch_hi=None, gamma=1.4, mu=0.0, prandtl=0.72, mech=None,
                  newton_max_iter=25, newton_tol=1e-13, device=0, volume="standard", rho_floor=0.0, p_floor=0.0,
-                 vib=None):
+                 vib=None, warp=0.0, bc=None, bc_state=None):
         self.lib = _abi.load()
         d = _abi.Desc()
         d.dim, d.degree = int(dim), int(degree)
@@ -88,6 +90,11 @@ class Solver:
         d.rho_floor, d.p_floor = float(rho_floor), float(p_floor)
         self._vib = vibration_struct(vib) if vib is not None else None
         d.vib = ctypes.pointer(self._vib) if self._vib is not None else None
+        d.warp = float(warp)
+        for q, kind in enumerate(bc or ()):
+            d.bc[q] = BC[kind] if isinstance(kind, str) else int(kind)
+        for q, val in enumerate(bc_state if bc_state is not None else ()):
+            d.bc_state[q] = float(val)
         self.device = torch.device("cuda", int(device))
         self.dim, self.N, self.batch = int(dim), int(degree), int(batch)
         self.physics, self.precision, self.volume = physics, precision, volume

@@ -56,6 +56,7 @@ int main(void) {
   printf("%zu %zu %zu\n", offsetof(dg_desc, rho_floor), offsetof(dg_desc, p_floor), offsetof(dg_counters, floored));
   printf("%zu %zu %zu %zu\n", offsetof(dg_desc, vib), sizeof(dg_vibration), offsetof(dg_vibration, park_sigma),
          offsetof(dg_vibration, two_temp));
+  printf("%zu %zu %zu\n", offsetof(dg_desc, warp), offsetof(dg_desc, bc), offsetof(dg_desc, bc_state));
   printf("%zu %zu %zu\n", offsetof(dg_mechanism, nu_f), offsetof(dg_mechanism, eff),
          offsetof(dg_mechanism, kappa_r));
   printf("%zu\n", offsetof(dg_counters, first_bad));
@@ -74,7 +75,7 @@ int main(void) {
               D.mech.offset, D.gamma.offset, D.newton_tol.offset, D.device.offset, D.patch_hi.offset,
               D.volume.offset, D.rho_floor.offset, D.p_floor.offset, C.floored.offset,
               D.vib.offset, ctypes.sizeof(_abi.Vibration), _abi.Vibration.park_sigma.offset,
-              _abi.Vibration.two_temp.offset, M.nu_f.offset, M.eff.offset, M.kappa_r.offset, C.first_bad.offset]
+              _abi.Vibration.two_temp.offset, D.warp.offset, D.bc.offset, D.bc_state.offset, M.nu_f.offset, M.eff.offset, M.kappa_r.offset, C.first_bad.offset]
     assert vals == expect
 
 

@@ -15,7 +15,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(_abi.LIB_PATH), reason="libdg
 
 def desc(dim=3, degree=3, nel=(4, 4, 4), physics=_abi.DG_EULER, precision=_abi.DG_F64, batch=1,
          patch=None, gamma=1.4, mu=0.0, prandtl=0.72, mech=None, volume=_abi.DG_VOLUME_STANDARD,
-         rho_floor=0.0, p_floor=0.0, vib=None):
+         rho_floor=0.0, p_floor=0.0, vib=None, warp=0.0, bc=None, bc_state=None):
     d = _abi.Desc()
     d.dim, d.degree, d.physics, d.precision, d.batch = dim, degree, physics, precision, batch
     for l in range(3):
@@ -34,6 +34,11 @@ def desc(dim=3, degree=3, nel=(4, 4, 4), physics=_abi.DG_EULER, precision=_abi.D
     d.newton_max_iter, d.newton_tol, d.device = 25, 1e-13, 0
     d.volume = volume
     d.rho_floor, d.p_floor = rho_floor, p_floor
+    d.warp = warp
+    for q, v in enumerate(bc or ()):
+        d.bc[q] = v
+    for q, v in enumerate(bc_state or ()):
+        d.bc_state[q] = v
     if vib == "air5":
         import dginputs as di
         from paper_2605_26388_amd.solver import vibration_struct
@@ -76,6 +81,15 @@ def create(d):
      _abi.DG_ERR_UNSUPPORTED, "floor"),
     (dict(physics=_abi.DG_REACTING_2T, dim=2, nel=(8, 8), mech="air5"), _abi.DG_ERR_ARG, "vib"),
     (dict(physics=_abi.DG_REACTING_2T, dim=3, mech="air5", vib="air5"), _abi.DG_ERR_UNSUPPORTED, "2-D"),
+    (dict(warp=0.3), _abi.DG_ERR_ARG, "warp"),
+    (dict(warp=float("nan")), _abi.DG_ERR_ARG, "warp"),
+    (dict(bc=(1, 0, 0, 0, 0, 0)), _abi.DG_ERR_ARG, "periodic"),
+    (dict(bc=(7, 7, 0, 0, 0, 0)), _abi.DG_ERR_ARG, "dg_bc"),
+    (dict(warp=0.05, physics=_abi.DG_NAVIER_STOKES), _abi.DG_ERR_UNSUPPORTED, "Euler"),
+    (dict(warp=0.05, precision=_abi.DG_F32), _abi.DG_ERR_UNSUPPORTED, "FP64"),
+    (dict(warp=0.05, volume=_abi.DG_VOLUME_SPLIT), _abi.DG_ERR_UNSUPPORTED, "standard"),
+    (dict(dim=2, nel=(8, 8), patch=((2, 2), (4, 4)), bc=(1, 1, 0, 0)), _abi.DG_ERR_UNSUPPORTED, "patch"),
+    (dict(bc=(2, 3, 0, 0, 0, 0), bc_state=(1.0, 0.0, 0.0, 0.0, -1.0)), _abi.DG_ERR_ARG, "bc_state"),
 ])
 def test_invalid_descriptors_rejected(kw, code, msg):
     rc, err = create(desc(**kw))
@@ -103,7 +117,8 @@ def test_null_arguments():
                                 dict(dim=2, nel=(8, 8), patch=((2, 2), (4, 4)), volume=_abi.DG_VOLUME_SPLIT,
                                      precision=_abi.DG_F32),
                                 dict(rho_floor=1e-6, p_floor=5e-7),
-                                dict(physics=_abi.DG_REACTING_2T, dim=2, nel=(8, 8), mech="air5", vib="air5")])
+                                dict(physics=_abi.DG_REACTING_2T, dim=2, nel=(8, 8), mech="air5", vib="air5"),
+                                dict(warp=0.05, bc=(1, 1, 2, 3, 0, 0), bc_state=(1.0, 0.0, 2.0, 0.0, 5.0))])
 def test_valid_descriptor_passes_the_checks(kw):
     rc, err = create(desc(**kw))
     # no device here: the only failure left is the device query itself

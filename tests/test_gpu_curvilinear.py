@@ -1,0 +1,130 @@
+"""GPU parity of the curvilinear stage (per-node metrics, boundary fluxes)
+against the oracle's CurvOperator: warped periodic meshes at several degrees
+in 2-D and 3-D, slip walls and supersonic in/outflow on warped meshes, free
+stream and conservation, batched stages, an SSPRK54 step, the warped node
+coordinates, the full 32^3 workload, and the unsupported combinations."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import dginputs as di
+from oracle.curvilinear import CurvMesh, CurvOperator
+from oracle.ssprk54 import ssprk54_step
+from oracle.timestep import rk_stage
+from helpers import to_gpu, from_gpu, rel_err
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-12
+G = 1.4
+
+
+def tol(N):
+    """The oracle (torch) and the library (host C++) evaluate the metric terms
+    independently; the 3-D conservative curl form applies D twice, so the
+    rounding difference of the metrics, and with it of the right-hand side,
+    grows with the degree: 1e-12 (1 + (N/4)^2)."""
+    return TOL64 * (1.0 + (N / 4.0) ** 2)
+
+
+def pair(dim, N, nel, lo, hi, warp, bc=None, bc_state=None, batch=1):
+    from paper_2605_26388_amd import Solver
+    m = CurvMesh(dim, N, nel, lo, hi, warp, bc=bc)
+    op = CurvOperator(m, bc_state=bc_state)
+    s = Solver(dim, N, nel, lo, hi, batch=batch, warp=warp, bc=bc, bc_state=bc_state)
+    assert s.E == m.base.E
+    return op, s
+
+
+def rand_state(op, seed, B=1, vmax=0.5):
+    rng = np.random.default_rng(seed)
+    shape = (B,) + tuple(op.mesh.X.shape[1:])
+    rho = rng.uniform(0.5, 1.5, shape)
+    vel = [rng.uniform(-vmax, vmax, shape) for _ in range(op.dim)]
+    p = rng.uniform(0.5, 1.5, shape)
+    return torch.tensor(np.stack([di.conserved_from_primitive(rho[b], [v[b] for v in vel], p[b], G)
+                                  for b in range(B)]))
+
+
+@pytest.mark.parametrize("dim,N", [(2, 1), (2, 3), (2, 5), (2, 7), (3, 1), (3, 2), (3, 3), (3, 4), (3, 6)])
+def test_curvilinear_rhs_parity_periodic(dim, N):
+    nel = (7, 5) if dim == 2 else (5, 3, 3)
+    lo, hi = (0.0,) * dim, (1.0, 1.3, 0.9)[:dim]
+    op, s = pair(dim, N, nel, lo, hi, 0.04)
+    U = rand_state(op, 10 + N)
+    err = rel_err(from_gpu(op, s.rhs(to_gpu(s, U))), op.rhs(U))
+    print(f"curvilinear dim {dim} N {N}: rel err {err:.3e}")
+    assert err < tol(N)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_curvilinear_rhs_parity_walls_and_inflow_outflow(dim):
+    nel = (6, 5) if dim == 2 else (4, 3, 3)
+    lo, hi = (0.0,) * dim, (1.0, 1.1, 0.9)[:dim]
+    walls = ("wall",) * (2 * dim)
+    op, s = pair(dim, 3, nel, lo, hi, 0.03, bc=walls)
+    U = rand_state(op, 21)
+    assert rel_err(from_gpu(op, s.rhs(to_gpu(s, U))), op.rhs(U)) < TOL64
+    ub = di.conserved_from_primitive(np.array([1.0]), [np.array([2.5])] + [np.array([0.2])] * (dim - 1),
+                                     np.array([1.0 / G]), G)[:, 0]
+    bc = ("inflow", "outflow") + ("wall", "wall") + ("periodic", "periodic") * (dim - 2)
+    op, s = pair(dim, 3, nel, lo, hi, 0.03, bc=bc, bc_state=ub)
+    U = rand_state(op, 22, vmax=0.3)
+    U[:, 1] = U[:, 1] + 2.0 * U[:, 0]                 # supersonic mean flow along x
+    U[:, -1] = U[:, -1] + 0.5 * ((U[:, 1] ** 2 - (U[:, 1] - 2.0 * U[:, 0]) ** 2) / U[:, 0])
+    assert rel_err(from_gpu(op, s.rhs(to_gpu(s, U))), op.rhs(U)) < TOL64
+
+
+def test_curvilinear_free_stream_and_conservation():
+    op, s = pair(3, 3, (6, 5, 4), (0, 0, 0), (1.0, 1.0, 1.0), 0.05)
+    c = s.empty()
+    c[:, 0], c[:, 1], c[:, 2], c[:, 3] = 1.1, 0.33, -0.22, 0.11
+    c[:, 4] = 0.9 / 0.4 + 0.5 * (0.33 ** 2 + 0.22 ** 2 + 0.11 ** 2) / 1.1
+    dc = s.rhs(c)
+    assert float(dc.abs().max()) < 1e-12 * 20.0
+    U = to_gpu(s, rand_state(op, 5))
+    dU = s.rhs(U)
+    I = s.integrals(dU)[:, :-1]
+    S = s.integrals(dU.abs())[:, :-1]
+    assert np.abs(I / S).max() < 1e-13
+
+
+def test_curvilinear_stage_batched_and_ssprk54():
+    op, s = pair(2, 3, (8, 6), (0, 0), (1.0, 1.0), 0.04, batch=2)
+    U0 = rand_state(op, 1, B=2)
+    Uk = rand_state(op, 2, B=2)
+    out = s.empty()
+    s.rk_stage(to_gpu(s, U0), to_gpu(s, Uk), out, 0.75, 0.25, 0.002)
+    assert rel_err(from_gpu(op, out), rk_stage(op, U0, Uk, 0.75, 0.25, 0.002)) < TOL64
+    Ug = to_gpu(s, U0)
+    s.ssprk54_step(Ug, 0.003)
+    assert rel_err(from_gpu(op, Ug), ssprk54_step(op, U0, 0.003)) < TOL64
+
+
+def test_curvilinear_node_coordinates():
+    op, s = pair(3, 3, (3, 2, 2), (0, 0, 0), (1.0, 2.0, 1.5), 0.06)
+    X = s.node_coords().cpu().reshape(op.mesh.X.shape)
+    assert float((X - op.mesh.X).abs().max()) < 1e-14
+
+
+def test_curvilinear_full_size_workload():
+    """32^3 warped periodic box, N = 3, the benchmark's curvilinear launch."""
+    p = di.PRESETS["euler3d"]
+    op, s = pair(3, 3, p["nel"], p["lo"], p["hi"], 0.03)
+    U = torch.tensor(di.random_euler(op.mesh.coords(), p["lo"], p["hi"]))[None]
+    Ug = to_gpu(s, U)
+    out = s.empty()
+    s.rk_stage(None, Ug, out, 0.0, 1.0, 1e-3)
+    assert rel_err(from_gpu(op, out), rk_stage(op, U, U, 0.0, 1.0, 1e-3)) < TOL64
+    assert s.status()["nonphysical"] == 0
+
+
+def test_curvilinear_adjoint_rejected():
+    from paper_2605_26388_amd._abi import DGError, DG_ERR_UNSUPPORTED
+    op, s = pair(3, 2, (2, 2, 2), (0, 0, 0), (1, 1, 1), 0.02)
+    U = to_gpu(s, rand_state(op, 3))
+    with pytest.raises(DGError) as e:
+        s.rhs_adjoint(U, s.empty())
+    assert e.value.code == DG_ERR_UNSUPPORTED
