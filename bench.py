@@ -369,6 +369,30 @@ def bench_reacting_2t(reps):
             "strang_step_ms": strang * 1e3}
 
 
+def bench_curvilinear(steps, warmup):
+    """Curvilinear stage on the headline mesh warped (warp 0.03, periodic),
+    FP64: mean launch time and the HBM roofline with the metric planes
+    (1/J and Ja^l: 10 doubles per node, read once per launch) added to the
+    state traffic."""
+    from paper_2605_26388_amd import Solver
+    p = di.PRESETS["euler3d"]
+    s = Solver(3, p["N"], p["nel"], p["lo"], p["hi"], warp=0.03)
+    X = s.node_coords().cpu().numpy()
+    U = torch.tensor(di.random_euler(X, p["lo"], p["hi"]))[None].to(s.device).contiguous()
+    dt = s.dt_cfl(U, p["cfl"])
+    wall, kern = time_stages(s, U, dt, steps, warmup)
+    st = s.status()
+    assert st["nonphysical"] == 0, st
+    nodes = s.E * s.Np
+    dof = nodes * s.nv
+    byt = WORDS_PER_DOF_STAGE * 8 * dof + 10 * 8 * nodes
+    s.close()
+    return {"workload": "euler3d warped: 3-D Euler 32^3, N=3, warp 0.03 (per-node metrics), periodic, FP64",
+            "kernel_us": kern * 1e6, "value": dof * 3 * steps / wall, "bytes_per_launch": byt,
+            "roofline": {"bound": "hbm", "achieved": byt / kern / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": byt / kern / 1e9 / HBM_PEAK_GBS}}
+
+
 def bench_adjoint(steps):
     """Adjoint workload (16^3, N=3, batch 8) in FP32: forward SSP-RK3 step vs
     its reverse sweep with stored stage states."""
@@ -405,7 +429,7 @@ def main():
     ap.add_argument("--only", choices=["f64", "f32"], default=None,
                     help="time one form only (profiling runs)")
     ap.add_argument("--side", choices=["adjoint", "navier_stokes", "navier_stokes_L", "reacting", "reacting_2t", "split",
-                                       "ssprk54"],
+                                       "ssprk54", "curvilinear"],
                     default=None,
                     help="instead: run one side workload alone and print its JSON (profiling runs)")
     ap.add_argument("--calib-copy", type=int, default=0,
@@ -434,7 +458,8 @@ def main():
               "reacting": lambda: bench_reacting(reps),
               "reacting_2t": lambda: bench_reacting_2t(reps),
               "split": lambda: bench_split(args.steps, args.warmup),
-              "ssprk54": lambda: bench_ssprk54(args.steps, args.warmup // 2)}[args.side]
+              "ssprk54": lambda: bench_ssprk54(args.steps, args.warmup // 2),
+              "curvilinear": lambda: bench_curvilinear(args.steps, args.warmup)}[args.side]
         print(json.dumps({args.side: fn()}), flush=True)
         return
 
@@ -505,6 +530,8 @@ def main():
         out["split"] = bench_split(args.steps, args.warmup)
         log("SSPRK54 workload ...")
         out["ssprk54"] = bench_ssprk54(args.steps, args.warmup // 2)
+        log("curvilinear workload ...")
+        out["curvilinear"] = bench_curvilinear(args.steps, args.warmup)
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(dict(p, N=3))
