@@ -3,18 +3,23 @@
  *
  * The library evaluates the semi-discrete operator dU/dt = L(U) of a nodal
  * discontinuous Galerkin spectral element method (tensor-product
- * Gauss-Lobatto-Legendre collocation) on periodic Cartesian meshes, fuses it
- * into the Shu-Osher Runge-Kutta stage, supplies the finite-rate chemistry
- * source and its implicit substep, and the discrete adjoint of L and of the
- * stage.  The operations follow the paper (MARUT, arXiv 2605.26388):
+ * Gauss-Lobatto-Legendre collocation) on periodic Cartesian meshes and on
+ * warped (curvilinear) meshes with boundary fluxes, fuses it into the
+ * Shu-Osher Runge-Kutta stage (also SSPRK54 with a per-stage positivity
+ * floor), supplies the finite-rate chemistry source (one or two temperatures)
+ * and its implicit substep, and the discrete adjoint of L and of the stage.
+ * The operations follow the paper (MARUT, arXiv 2605.26388):
  *   - the semi-discrete system and the SSP-RK stage: SSP-RK Time
  *     Discretization appendix;
  *   - the volume integral and surface lift: eqs. vol_weak and surf_int of the
  *     Kernel Architecture for Hyperbolic Terms section, with the Rusanov flux
- *     of its Surface Fluxes paragraph and 2:1 mortars;
+ *     of its Surface Fluxes paragraph and 2:1 mortars; the entropy-conservative
+ *     split form eq. vol_split with Ranocha's flux; curvilinear metrics and
+ *     boundary fluxes of the same section;
  *   - BR1 viscous terms: eqs. br1_avg, tau and br1_flux (Parabolic Terms);
  *   - the source and its implicit substep: eqs. src_reaction_rate, src_omega,
- *     strang_split and source_residual (Source Terms).
+ *     strang_split and source_residual (Source Terms), with the two-temperature
+ *     terms of eq. src_landau_teller (Thermochemical non-equilibrium).
  *
  * Conventions shared by every call
  *   Layout.  Every state-like buffer (U, dUdt, adjoint variables) is
@@ -24,7 +29,8 @@
  *     four children (0,0), (1,0), (0,1), (1,1) in place.  dtype is the
  *     context's precision: double (DG_F64) or float (DG_F32).
  *   Variables.  Euler / Navier-Stokes: (rho, rho u, rho v[, rho w], E).
- *     Reacting Euler (2-D): (rho_1..rho_Ns, rho u, rho v, E).
+ *     Reacting Euler (2-D): (rho_1..rho_Ns, rho u, rho v, E), and E_v last
+ *     with two temperatures.
  *   Ownership.  State buffers are device memory owned by the caller; the
  *     library neither frees nor retains them past the call.  The context owns
  *     its tables, constants, scratch and status counters, so a context serves
@@ -36,8 +42,8 @@
  *     forbidden aliasing) are returned synchronously before any launch as
  *     DG_ERR_ARG or DG_ERR_UNSUPPORTED; a failed launch returns DG_ERR_HIP.
  *     Device-side numerical faults (non-physical state, Newton failure,
- *     species clipping) never abort a launch: they are sticky counters read
- *     by dg_status_read.  dg_last_error() describes the last failure of the
+ *     species clipping) and positivity-floor activity never abort a launch:
+ *     they are sticky counters read by dg_status_read.  dg_last_error() describes the last failure of the
  *     calling thread.
  */
 #ifndef DG_H
