@@ -26,11 +26,12 @@
 // and output are those of the standard form.
 //
 // FP32 form: states and the LDS flux operand are float, the D-sweep is a
-// float FMA chain.  Primitive recovery, flux evaluation and the face
-// corrections (F* - F) stay in double; before rounding to float the volume
-// flux has the flux of the element's first node subtracted, which leaves
-// sum_m D_im F_m unchanged (D annihilates constants) but keeps the rounding
-// error relative to the variation inside the element.
+// float FMA chain, and dU/dt and the stage combination accumulate in float.
+// Primitive recovery, flux evaluation and the face corrections (F* - F) stay
+// in double; before rounding to float the volume flux has the flux of the
+// element's first node subtracted, which leaves sum_m D_im F_m unchanged (D
+// annihilates constants) but keeps the rounding error relative to the
+// variation inside the element.
 #include <type_traits>
 
 #include "dg_device.hpp"
@@ -320,20 +321,10 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
     }
   }
   };
-  // the split form loads them after its volume sweep instead: they would
-  // stay live in registers through the sweep's two-point fluxes
-  if constexpr (!SPLIT) load_neighbours();
-  // stage input U0, fetched early as well
+  // The neighbour states are loaded after the volume sweep and U0 only for
+  // the output: held from the start they would stay live in registers
+  // through the sweep (measured: 4 waves per SIMD instead of 5, and slower).
   const bool use_u0 = (sp.mode != 0) && (sp.a != 0.0);
-  double u0[NV];
-  if (use_u0) {
-    const rsrc_t r0 = make_rsrc(static_cast<const T*>(sp.U0) + (size_t)b * NV * plane, abytes);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) u0[v] = Buf<T>::load(r0, off, v * pstride);
-  } else {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) u0[v] = 0.0;
-  }
 
   Thermo th;
   const bool ok = PHYS::thermo(u, th, pc);
@@ -391,9 +382,12 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
   __syncthreads();
 
   // ---- volume integral: -sum_l (2/h_l) sum_m D_im F_l,m ----------------
-  double acc[NV];
+  // accumulator of dU/dt: float in the FP32 form (its stage output is rounded
+  // to float anyway; half the registers and no conversions), else double
+  using AT = typename std::conditional<SPLIT, double, T>::type;
+  AT acc[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  for (int v = 0; v < NV; ++v) acc[v] = AT(0);
   if constexpr (SPLIT) {
     const double gm1i = 1.0 / (pc.gamma - 1.0);
     bool far = false;
@@ -426,12 +420,12 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
         T s = 0;
 #pragma unroll
         for (int m = 0; m < n; ++m) s = fma(drow[m], sF[l][v][base + m * st], s);
-        acc[v] = fma(-g[l], static_cast<double>(s), acc[v]);
+        acc[v] = fma(AT(-g[l]), static_cast<AT>(s), acc[v]);
       }
     }
   }
 
-  if constexpr (SPLIT) load_neighbours();
+  load_neighbours();
 
   // ---- surface lift (eq. surf_int) ----------------------------------------
   const double aown = wave_sound<PHYS, F32>(th);
@@ -471,7 +465,7 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
     }
     const double sc = (side[l] == 1 ? -g[l] : g[l]) * hwinv;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] = fma(sc, Dv[v], acc[v]);
+    for (int v = 0; v < NV; ++v) acc[v] = fma(AT(sc), AT(Dv[v]), acc[v]);
     if constexpr (SPLIT) {
       // the split sum's m = i term, 2 D_ii F_l(U_i)
       const double cd = -2.0 * g[l] * static_cast<double>(sD[ii[l] * (n + 1)]);
@@ -487,15 +481,27 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) Buf<T>::store(ro, off, acc[v], v * pstride);
     } else {
-      double r[NV];
+      double u0[NV];
+      if (use_u0) {
+        const rsrc_t r0 = make_rsrc(static_cast<const T*>(sp.U0) + (size_t)b * NV * plane, abytes);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) u0[v] = Buf<T>::load(r0, off, v * pstride);
+      }
+      AT r[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        r[v] = fma(sp.c, acc[v], sp.b * u[v]);
-        if (use_u0) r[v] = fma(sp.a, u0[v], r[v]);
+        r[v] = fma(AT(sp.c), acc[v], AT(sp.b) * AT(u[v]));
+        if (use_u0) r[v] = fma(AT(sp.a), AT(u0[v]), r[v]);
       }
       if constexpr (std::is_same<PHYS, EulerPhys<DIM>>::value) {
-        if (sp.rho_min > 0.0 || sp.p_min > 0.0)
-          positivity_floor(r, sp.rho_min, sp.p_min, 1.0 / (pc.gamma - 1.0), mv.counters);
+        if (sp.rho_min > 0.0 || sp.p_min > 0.0) {  // the floor itself in double
+          double rd[NV];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) rd[v] = r[v];
+          positivity_floor(rd, sp.rho_min, sp.p_min, 1.0 / (pc.gamma - 1.0), mv.counters);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) r[v] = AT(rd[v]);
+        }
       }
 #pragma unroll
       for (int v = 0; v < NV; ++v) Buf<T>::store(ro, off, r[v], v * pstride);
@@ -505,8 +511,8 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
         const rsrc_t rv = make_rsrc(static_cast<const T*>(use_v ? sp.V : sp.Uk) + (size_t)b * NV * plane, abytes);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          double w = fma(sp.c2, acc[v], sp.b2 * u[v]);
-          if (use_v) w = fma(sp.a2, Buf<T>::load(rv, off, v * pstride), w);
+          AT w = fma(AT(sp.c2), acc[v], AT(sp.b2) * AT(u[v]));
+          if (use_v) w = fma(AT(sp.a2), AT(Buf<T>::load(rv, off, v * pstride)), w);
           Buf<T>::store(r2, off, w, v * pstride);
         }
       }
