@@ -464,6 +464,14 @@ MeshView mesh_view(const Ctx& c) {
   m.nrows = c.nrows;
   m.counters = c.d_counters;
   m.first_bad = c.d_first_bad;
+  if (c.dim == 3) {  // 3-D meshes have no refined patch
+    const int nz = c.desc.nel[2];
+    const int sh = nz % 4 == 0 ? 2 : (nz % 2 == 0 ? 1 : -1);
+    if (sh >= 0) {
+      m.zf_shift = sh;
+      m.zf_plane = c.desc.nel[0] * c.desc.nel[1];
+    }
+  }
   return m;
 }
 }  // namespace dg

@@ -40,6 +40,30 @@ __device__ __forceinline__ int xcd_remap(int w, int nblocks) {
   return (xcd < r) ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
 }
 
+// Order of the element blocks inside each XCD's range.  In lexicographic
+// order the z-neighbour of an element is a whole plane (nx*ny elements) away
+// in time, beyond what the XCD's L2 keeps while the other streams of the
+// stage pass through it; taking groups of dz whole z-planes with z fastest
+// (then x, then y) brings the z-neighbour to the adjacent block and the x- and
+// y-neighbours to within dz and dz*nx blocks.  Only for one element per block
+// (the block index is the element index); a bijection of [0, E) when dz
+// divides nz, which the host ensures.  The Cartesian stage kernel uses it
+// (measured: 16 % fewer bytes fetched, 1 % faster); the curvilinear,
+// Navier-Stokes and adjoint kernels, which stream more arrays per element,
+// measured 1-2 % slower with it and keep the plain order.
+template <int EPB>
+__device__ __forceinline__ int zfast_block(int eb, const MeshView& mv) {
+  if constexpr (EPB != 1) {
+    return eb;
+  } else {
+    if (mv.zf_plane == 0) return eb;
+    const unsigned dz = 1u << mv.zf_shift;
+    const unsigned G = dz * (unsigned)mv.zf_plane;
+    const unsigned g = (unsigned)eb / G, t = (unsigned)eb - g * G;
+    return (int)(g * G + (t & (dz - 1)) * (unsigned)mv.zf_plane + (t >> mv.zf_shift));
+  }
+}
+
 __device__ __forceinline__ void report_nonphysical(int* counters, unsigned long long* first_bad,
                                                    unsigned long long flat) {
   atomicAdd(&counters[CNT_NONPHYSICAL], 1);

@@ -45,6 +45,10 @@ struct MeshView {
   int nrows;
   int* counters;
   unsigned long long* first_bad;
+  // 3-D Cartesian meshes (lexicographic element order, x fastest): element
+  // blocks are taken in groups of 2^zf_shift whole z-planes of zf_plane
+  // elements each, z fastest inside a group; zf_plane = 0 keeps the order
+  int zf_shift = 0, zf_plane = 0;
 };
 
 // One 2:1 non-conforming face (2-D): coarse element, direction, side of the

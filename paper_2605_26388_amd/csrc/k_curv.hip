@@ -101,33 +101,7 @@ k_stage_curv(StageParams sp, MeshView mv, PhysConst pc, CurvArgs ca) {
 #pragma unroll
     for (int d = 0; d < DIM; ++d) Ja[l][d] = ca.met[(2 + l * DIM + d) * plane + at];
 
-  // neighbour's matching node on conforming faces (lanes on a face only)
-  int side[DIM];
-  double un[DIM][NV];
-#pragma unroll
-  for (int l = 0; l < DIM; ++l) {
-    side[l] = (ii[l] == 0) ? 0 : ((ii[l] == N) ? 1 : -1);
-    const int ne = side[l] >= 0 ? nbl[2 * l + side[l]] : -1;
-    if (ne >= 0) {
-      const int shift = side[l] == 1 ? -N : N;
-      const unsigned noff = (unsigned)(ne * NP + node + shift * stride[l]);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) un[l][v] = Buf<double>::load(rU, noff, v * pstride);
-    } else {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) un[l][v] = u[v];
-    }
-  }
   const bool use_u0 = (sp.mode != 0) && (sp.a != 0.0);
-  double u0[NV];
-  if (use_u0) {
-    const rsrc_t r0 = make_rsrc(static_cast<const double*>(sp.U0) + (size_t)b * NV * plane, abytes);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) u0[v] = Buf<double>::load(r0, off, v * pstride);
-  } else {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) u0[v] = 0.0;
-  }
 
   Thermo th;
   const bool ok = PHYS::thermo(u, th, pc);
@@ -170,6 +144,26 @@ k_stage_curv(StageParams sp, MeshView mv, PhysConst pc, CurvArgs ca) {
         for (int m = 0; m < n; ++m) s = fma(drow[m], sF[l][v][base + m * st], s);
         acc[v] -= s;
       }
+    }
+  }
+
+  // Neighbour's matching node on conforming faces (lanes on a face only),
+  // loaded after the volume sweep and U0 only for the output: held from the
+  // start they would stay live in registers through the sweep.
+  int side[DIM];
+  double un[DIM][NV];
+#pragma unroll
+  for (int l = 0; l < DIM; ++l) {
+    side[l] = (ii[l] == 0) ? 0 : ((ii[l] == N) ? 1 : -1);
+    const int ne = side[l] >= 0 ? nbl[2 * l + side[l]] : -1;
+    if (ne >= 0) {
+      const int shift = side[l] == 1 ? -N : N;
+      const unsigned noff = (unsigned)(ne * NP + node + shift * stride[l]);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) un[l][v] = Buf<double>::load(rU, noff, v * pstride);
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) un[l][v] = u[v];
     }
   }
 
@@ -249,6 +243,12 @@ k_stage_curv(StageParams sp, MeshView mv, PhysConst pc, CurvArgs ca) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) Buf<double>::store(ro, off, acc[v], v * pstride);
     } else {
+      double u0[NV];
+      if (use_u0) {
+        const rsrc_t r0 = make_rsrc(static_cast<const double*>(sp.U0) + (size_t)b * NV * plane, abytes);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) u0[v] = Buf<double>::load(r0, off, v * pstride);
+      }
       double r[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {

@@ -253,7 +253,7 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
   const int nEB = (E + EPB - 1) / EPB;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int b = blk / nEB;
-  const int eb = blk - b * nEB;
+  const int eb = zfast_block<EPB>(blk - b * nEB, mv);
   const int el = tid / NP;
   const int node = tid - el * NP;
   int e = eb * EPB + el;
