@@ -32,6 +32,19 @@ def test_rhs_parity_all_degrees(dim, N):
     assert rel_err(got, ref) < TOL64
 
 
+@pytest.mark.parametrize("N,nel", [(3, (3, 2, 2)), (3, (2, 3, 6)), (3, (3, 3, 4)), (3, (2, 2, 8)), (5, (3, 2, 2)),
+                                   (4, (2, 3, 4))])
+def test_rhs_parity_block_orders(N, nel):
+    """3-D meshes whose z-count selects each order of the element blocks
+    (groups of 2 or 4 z-planes taken z fastest; plain order for odd counts is
+    covered above), batched so that a group boundary falls between members."""
+    op, s = make_pair(3, N, nel, (0.0, 0.0, 0.0), (1.0, 0.8, 1.2), batch=2)
+    U = random_euler_state(op, 40 + N, B=2)
+    ref = op.rhs(U)
+    got = from_gpu(op, s.rhs(to_gpu(s, U)))
+    assert rel_err(got, ref) < TOL64
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_rk_stage_parity_batched(dim):
     nel = (6, 9) if dim == 2 else (4, 5, 3)
