@@ -312,12 +312,9 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
     const int ne = conf ? nbe[l] : ec;
     const int shift = side[l] == 1 ? -N : (side[l] == 0 ? N : 0);
     const unsigned noff = (unsigned)(ne * NP + node + shift * stride[l]);
-    if (!MASK_FACES || side[l] >= 0) {
+    if (!MASK_FACES || side[l] >= 0) {  // masked lanes never read un[l]
 #pragma unroll
       for (int v = 0; v < NV; ++v) un[l][v] = Buf<T>::load(rU, noff, v * pstride);
-    } else {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) un[l][v] = 0.0;
     }
   }
   };
@@ -451,7 +448,8 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
     const double co = fabs(vel[l]) + aown;
     const double cn = fabs(vn) + wave_sound<PHYS, F32>(tn);
     const double lam = co >= cn ? co : cn;
-    const double hs = side[l] == 1 ? lam : -lam;
+    const double sgn = side[l] == 1 ? 1.0 : -1.0;  // +1 on the +xi_l face
+    const double hs = sgn * lam;
 #pragma unroll
     for (int v = 0; v < NV; ++v) Dv[v] = fma(-hs, un[l][v] - u[v], Fn[v] - Fo[v]);
     if constexpr (MORTAR) {
@@ -463,7 +461,7 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
         for (int v = 0; v < NV; ++v) Dv[v] = 2.0 * (src[v] - Fo[v]);
       }
     }
-    const double sc = (side[l] == 1 ? -g[l] : g[l]) * hwinv;
+    const double sc = -sgn * (g[l] * hwinv);
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = fma(AT(sc), AT(Dv[v]), acc[v]);
     if constexpr (SPLIT) {
