@@ -121,28 +121,12 @@ k_adjoint(AdjParams ap, MeshView mv, PhysConst pc) {
     lam[v] = Buf<T>::load(rL[v], off);
   }
   int side[DIM], nbe[DIM];
-  double un[DIM][NV], ln[DIM][NV];
 #pragma unroll
   for (int l = 0; l < DIM; ++l) {
     side[l] = (ii[l] == 0) ? 0 : ((ii[l] == N) ? 1 : -1);
     nbe[l] = (active && side[l] >= 0) ? nbl[2 * l + side[l]] : -1;
-    if (nbe[l] >= 0) {
-      const unsigned noff = (unsigned)(nbe[l] * NP + node + (side[l] ? -N : N) * stride[l]);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        un[l][v] = Buf<T>::load(rU[v], noff);
-        ln[l][v] = Buf<T>::load(rL[v], noff);
-      }
-    }
   }
-  double l0[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) l0[v] = 0.0;
   T* lam0b = ap.lam_0 ? static_cast<T*>(ap.lam_0) + bo : nullptr;
-  if (active && (ap.mode == 0 || ap.mode == 1)) {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) l0[v] = Buf<T>::load(make_rsrc(lam0b + v * plane, pbytes), off);
-  }
 
   Thermo th;
   PHYS::thermo(u, th, pc);
@@ -170,6 +154,18 @@ k_adjoint(AdjParams ap, MeshView mv, PhysConst pc) {
   if (tid < S::NT) {
 #pragma unroll
     for (int l = 0; l < DIM; ++l) {
+      // the neighbour's state and adjoint for this direction only (all three
+      // held from the start took 3 waves per SIMD instead of 4 in FP32, and
+      // the FP32 reverse sweep 10 % longer)
+      double unl[NV], lnl[NV];
+      if (nbe[l] >= 0) {
+        const unsigned noff = (unsigned)(nbe[l] * NP + node + (side[l] ? -N : N) * stride[l]);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          unl[v] = Buf<T>::load(rU[v], noff);
+          lnl[v] = Buf<T>::load(rL[v], noff);
+        }
+      }
       const int il = ii[l], st = stride[l];
       const int base = tid - il * st;
       T drow[n];
@@ -188,8 +184,8 @@ k_adjoint(AdjParams ap, MeshView mv, PhysConst pc) {
         const bool ownL = side[l] == 1;
         // neighbour thermodynamics (same sequence as the forward stage)
         Thermo tn;
-        PHYS::thermo(un[l], tn, pc);
-        const double vn = un[l][1 + l] * tn.ri;
+        PHYS::thermo(unl, tn, pc);
+        const double vn = unl[1 + l] * tn.ri;
         const double co = fabs(vel[l]) + aown;
         const double cn = fabs(vn) + sound<PHYS>(tn);
         const double lamx = co >= cn ? co : cn;
@@ -198,9 +194,9 @@ k_adjoint(AdjParams ap, MeshView mv, PhysConst pc) {
         double mu[NV], dU = 0.0;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          mu[v] = sc * (lam[v] - ln[l][v]);
+          mu[v] = sc * (lam[v] - lnl[v]);
           // (U_R - U_L) . mu
-          const double jump = ownL ? (un[l][v] - u[v]) : (u[v] - un[l][v]);
+          const double jump = ownL ? (unl[v] - u[v]) : (u[v] - unl[v]);
           dU = fma(jump, mu[v], dU);
         }
         // own-flux lift term and half of the flux Jacobian of F*
@@ -233,6 +229,13 @@ k_adjoint(AdjParams ap, MeshView mv, PhysConst pc) {
   }
 
   if (active) {
+    double l0[NV];  // lambda_0 in, loaded only here
+#pragma unroll
+    for (int v = 0; v < NV; ++v) l0[v] = 0.0;
+    if (ap.mode == 0 || ap.mode == 1) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) l0[v] = Buf<T>::load(make_rsrc(lam0b + v * plane, pbytes), off);
+    }
     T* lkb = static_cast<T*>(ap.lam_k) + bo;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
