@@ -437,7 +437,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU; multi-GPU runs are not part of it "
+        print("bench.py: measures one GPU; runs on several GPUs are not supported "
               f"(--gpus {args.gpus} requested)", file=sys.stderr)
         sys.exit(2)
     if args.calib_copy:
