@@ -178,6 +178,35 @@ def test_positivity_floor_on_stage_outputs(physics):
     assert s.status()["floored"] == 0
 
 
+def test_positivity_floor_fp32_form():
+    """FP32 form: the stage combination in float, the floor itself in double,
+    the result rounded to float.  The floored output matches the oracle's
+    floored FP64 stage at the same (float) state to the form's accuracy, and
+    the bounds hold up to float rounding."""
+    rmin, pmin = 1e-6, 5e-7
+    op, _ = make_pair(3, 3, (4, 4, 3), (0, 0, 0), (TWO_PI,) * 3)
+    from paper_2605_26388_amd import Solver
+    sf = Solver(3, 3, (4, 4, 3), (0, 0, 0), (TWO_PI,) * 3, precision="f32", rho_floor=rmin, p_floor=pmin)
+    U = _near_vacuum_state(op, 7).float().double()
+    dt = 2e-3
+    raw = rk_stage(op, U, U, 0.0, 1.0, dt)
+    ref = positivity_floor(raw, 1.4, rmin, pmin)
+    nfloored = int((ref != raw).any(dim=1).sum())
+    assert nfloored > 0
+    sf.status(reset=True)
+    out = sf.empty()
+    sf.rk_stage(None, to_gpu(sf, U), out, 0.0, 1.0, dt)
+    got = from_gpu(op, out)
+    err = rel_err(got, ref)
+    print(f"FP32 floored stage error: {err:.3e}; floored {sf.status()['floored']} (oracle {nfloored})")
+    assert err < 1e-5
+    assert abs(sf.status()["floored"] - nfloored) <= max(1, nfloored // 100)
+    P = op.phys.prims(got)
+    assert float(P["rho"].min()) >= rmin * (1 - 2.0 ** -23)
+    slack = 8 * 2.0 ** -24 * 0.4 * P["E"].abs()
+    assert bool((P["p"] >= pmin - slack).all())
+
+
 def test_floored_ssprk54_step():
     rmin, pmin = 1e-6, 5e-7
     op, _ = make_pair(3, 3, (4, 3, 3), (0, 0, 0), (TWO_PI,) * 3)
