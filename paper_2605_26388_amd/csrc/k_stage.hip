@@ -214,6 +214,63 @@ __device__ __forceinline__ void split_sweep(int tid, const int (&ii)[3], const i
   }
 }
 
+// Fast split sum with every unordered pair of a line evaluated once (the
+// two-point flux is symmetric): for k = 1 .. (n-1)/2 the lane evaluates
+// F#_l(U_i, U_{i+k}) and hands it to the lane of node i+k, which adds
+// D_{i+k,i} times it; for even n the opposite partner i + n/2 is evaluated by
+// both of its lanes.  A lane thus makes floor(n/2) flux evaluations per
+// direction instead of n - 1 (two instead of three at N = 3).  A pair's
+// far flag travels with its flux, so both lanes of a far pair redo their sums
+// in the exact form.  The hand-over is a lane shuffle, so a whole line must
+// lie in one wave (one-wave workgroups).
+template <int DIM, int N, int l, int W>
+__device__ __forceinline__ void split_sweep_pairs(int tid, const int (&ii)[3], const int (&stride)[3],
+                                                  const SplitNode<DIM>& a, const double (*Q)[W], const double* sD,
+                                                  const double (&g)[DIM], double gm1i, bool& far,
+                                                  double (&acc)[DIM + 2]) {
+  if constexpr (l < DIM) {
+    constexpr int NV = DIM + 2, n = N + 1, K1 = (n - 1) / 2;
+    const int il = ii[l];
+    const int st = stride[l];
+    const int base = tid - il * st;
+    const int lbase = (tid & 63) - il * st;  // wave lane of the line's node 0
+    double s[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) s[v] = 0.0;
+#pragma unroll
+    for (int k = 1; k <= K1; ++k) {
+      const int m = il + k < n ? il + k : il + k - n;   // partner evaluated here
+      const int j = il - k >= 0 ? il - k : il - k + n;  // partner whose flux arrives
+      double F[NV];
+      bool fp = false;
+      ranocha_flux<DIM, l, false>(a, Q, tid, base + m * st, gm1i, fp, F);
+      const double dm = sD[il * n + m];
+      const double dj = sD[il * n + j];
+      const int src = lbase + j * st;
+      const int fr = __shfl(fp ? 1 : 0, src);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double Fr = __shfl(F[v], src);
+        s[v] = fma(dm, F[v], s[v]);
+        s[v] = fma(dj, Fr, s[v]);
+      }
+      far = far || fp || fr != 0;
+    }
+    if constexpr (n % 2 == 0) {
+      const int m = il + n / 2 < n ? il + n / 2 : il - n / 2;
+      double F[NV];
+      ranocha_flux<DIM, l, false>(a, Q, tid, base + m * st, gm1i, far, F);
+      const double dm = sD[il * n + m];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) s[v] = fma(dm, F[v], s[v]);
+    }
+    const double c = -2.0 * g[l];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = fma(c, s[v], acc[v]);
+    split_sweep_pairs<DIM, N, l + 1>(tid, ii, stride, a, Q, sD, g, gm1i, far, acc);
+  }
+}
+
 // register budget: four waves per SIMD; the reacting physics (eight
 // variables, mortar faces, 77,824-node workloads) takes three, which it needs
 // to keep its face state in registers, and so does the split form, whose
@@ -388,7 +445,12 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
   if constexpr (SPLIT) {
     const double gm1i = 1.0 / (pc.gamma - 1.0);
     bool far = false;
-    if (tid < S::NT) split_sweep<DIM, N, 0, false>(tid, ii, stride, own, sQ, sD, g, gm1i, far, acc);
+    if (tid < S::NT) {
+      if constexpr (S::BS == 64)
+        split_sweep_pairs<DIM, N, 0>(tid, ii, stride, own, sQ, sD, g, gm1i, far, acc);
+      else
+        split_sweep<DIM, N, 0, false>(tid, ii, stride, own, sQ, sD, g, gm1i, far, acc);
+    }
     if (far) sFar = 1;
     __syncthreads();
     if (sFar) {  // block-uniform: some pair is too far apart for the series
