@@ -22,8 +22,10 @@
 // form: log means of rho and rho/p, arithmetic means of v and p, the crossed
 // pressure-velocity product in the energy row).  The m = i term, D_ii F_l(U_i),
 // is nonzero only at the line's end nodes (GLL: D_ii = 0 inside), so it is
-// added in the face step, which computes F_l(U_i) there anyway.  Faces, lift
-// and output are those of the standard form.
+// added in the face step, which computes F_l(U_i) there anyway.  Where a line
+// lies in one wave, each unordered pair is evaluated by one of its two lanes
+// and handed to the other by a lane shuffle.  Faces, lift and output are
+// those of the standard form.
 //
 // FP32 form: states and the LDS flux operand are float, the D-sweep is a
 // float FMA chain, and dU/dt and the stage combination accumulate in float.
@@ -183,8 +185,10 @@ __device__ __forceinline__ void split_term(int k, int tid, int il, int base, int
 // acc -= 2 (2/h_l) sum_{m != i} D_im F#_l(U_i, U_m) over the lane's line along
 // l.  The partner index runs i+1, ..., i+N modulo n, so every lane makes the
 // same N flux evaluations per direction (the m = i term is added elsewhere).
-// The fast form is fully unrolled; the exact form keeps its partner loop
-// rolled (it only runs for lanes with widely separated partner states).
+// This serves the exact form, and the fast form where a line spans waves
+// (split_sweep_pairs below halves the evaluations otherwise).  The fast form
+// is fully unrolled; the exact form keeps its partner loop rolled (it only
+// runs for lanes with widely separated partner states).
 template <int DIM, int N, int l, bool EXACT, int W>
 __device__ __forceinline__ void split_sweep(int tid, const int (&ii)[3], const int (&stride)[3],
                                             const SplitNode<DIM>& a, const double (*Q)[W], const double* sD,
