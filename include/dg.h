@@ -72,6 +72,13 @@ enum dg_status {
  * DG_REACTING_2T: translational-rotational T and vibrational T_v (Thermochemical
  *   non-equilibrium section): the state gains E_v (last variable). */
 enum dg_physics { DG_EULER = 0, DG_NAVIER_STOKES = 1, DG_REACTING_EULER = 2, DG_REACTING_2T = 3 };
+/* DG_F64: state in double, every step in double.
+ * DG_F32 (the FP32 form): state buffers in float.  Primitive recovery and its
+ *   positivity checks, the physical and interface fluxes, the face corrections,
+ *   the chemistry source and the reductions stay in double; the volume sweep
+ *   operand (the element's fluxes less those of its first node), the
+ *   accumulation of dU/dt and the stage combination are float.  The split form
+ *   sums in double in both. */
 enum dg_precision { DG_F64 = 0, DG_F32 = 1 };
 
 /* Volume integral of the Euler operator.
