@@ -78,7 +78,7 @@ enum dg_physics { DG_EULER = 0, DG_NAVIER_STOKES = 1, DG_REACTING_EULER = 2, DG_
  *   the chemistry source and the reductions stay in double; the volume sweep
  *   operand (the element's fluxes less those of its first node), the
  *   accumulation of dU/dt and the stage combination are float.  The split form
- *   sums in double in both. */
+ *   keeps its sweep, accumulation and stage combination in double in both. */
 enum dg_precision { DG_F64 = 0, DG_F32 = 1 };
 
 /* Volume integral of the Euler operator.
