@@ -35,7 +35,9 @@ class DGRollout(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gU):
         s, dt = ctx.solver, ctx.dt
-        lam = gU.contiguous().to(s.dtype)
+        # lam and nxt swap roles every step and the reverse sweep writes into
+        # nxt: both are the binding's own buffers, never the caller's gradient
+        lam = gU.to(s.dtype, copy=True).contiguous()
         nxt = s.empty()
         acc, mu2, mu1 = s.empty(), s.empty(), s.empty()
         for st in reversed(ctx.saved_states):
