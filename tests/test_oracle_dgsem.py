@@ -176,13 +176,13 @@ def l2_density_error(op, U, Uex):
 
 def test_vortex_convergence_order():
     """Isentropic vortex, N=3, fixed end time, small CFL so the SSP-RK3 time
-    error does not mask the spatial order.  At the resolutions reachable here
-    (h >= 0.3125, under 3 elements per vortex radius) the measured order is
-    about 3.2, pre-asymptotic for N+1 = 4; a dropped or mis-weighted surface
-    term falls to order <= 2, which this bound rejects."""
+    error does not mask the spatial order.  Measured L2(rho) errors 1.61e-4,
+    1.75e-5, 1.39e-6 on 16^2, 32^2, 64^2: orders 3.20 and 3.65, approaching
+    N+1 = 4 once the vortex core (radius about 1) spans several elements; a
+    dropped or mis-weighted surface term falls to order <= 2."""
     tend = 0.35
     errs = []
-    for ne in (8, 16, 32):
+    for ne in (16, 32, 64):
         op = euler_op(2, 3, (ne, ne), (-5, -5), (5, 5))
         X = op.mesh.coords()
         U = torch.tensor(di.vortex(X, 0.0))[None]
@@ -193,7 +193,8 @@ def test_vortex_convergence_order():
         errs.append(l2_density_error(op, U, torch.tensor(di.vortex(X, tend))[None]))
     eoc = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert errs[0] > errs[1] > errs[2]
-    assert 3.0 <= eoc[1] <= 4.7, eoc
+    assert 3.0 <= eoc[0] <= 4.7, eoc
+    assert 3.5 <= eoc[1] <= 4.7, eoc
 
 
 def test_entropy_wave_3d_converges():
