@@ -78,8 +78,15 @@ class CurvMesh:
         self.w = torch.tensor(w)
         X = warp(self.base.coords(), lo, hi, A)
         self.X = torch.tensor(X)                                        # (dim, E, n..n)
+        # The metric terms are taken from coordinates relative to each
+        # element's first node: D annihilates constants, and the curl of a
+        # constant times a gradient vanishes (the tensor-product derivatives
+        # of different directions commute), so the terms are unchanged in
+        # exact arithmetic, while their rounding is relative to the element's
+        # size instead of its distance from the origin.
+        Xl = self.X - self.X.reshape(dim, self.base.E, -1)[:, :, :1].reshape((dim, self.base.E) + (1,) * dim)
         # dX[d][m] = d X_d / d xi_m at every node
-        dX = [[dsweep(self.X[d][None, None], self.D, dim, m)[0, 0] for m in range(dim)] for d in range(dim)]
+        dX = [[dsweep(Xl[d][None, None], self.D, dim, m)[0, 0] for m in range(dim)] for d in range(dim)]
         if dim == 2:
             self.Ja = [torch.stack([dX[1][1], -dX[0][1]]), torch.stack([-dX[1][0], dX[0][0]])]
             self.J = dX[0][0] * dX[1][1] - dX[0][1] * dX[1][0]
@@ -89,7 +96,7 @@ class CurvMesh:
             Ja = [[None] * 3 for _ in range(3)]
             for nn in range(3):
                 mm, ll = (nn + 1) % 3, (nn + 2) % 3
-                V = [self.X[ll] * dX[mm][k] for k in range(3)]          # X_l grad X_m
+                V = [Xl[ll] * dX[mm][k] for k in range(3)]             # X_l grad X_m
                 for i in range(3):
                     curl_i = dxi(V[(i + 2) % 3], (i + 1) % 3) - dxi(V[(i + 1) % 3], (i + 2) % 3)
                     Ja[i][nn] = -curl_i
