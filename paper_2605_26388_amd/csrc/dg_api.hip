@@ -377,7 +377,7 @@ static bool build_curv(const dg_desc& d, const Ctx& c, const MeshBuild& mb, std:
   xyz.assign((size_t)dim * P, 0.0);
   const double* D = c.h_K.D;
   const int stride[3] = {1, n, n * n};
-  std::vector<double> X(3 * NP), dX(9 * NP), V(3 * NP);
+  std::vector<double> X(3 * NP), Xl(3 * NP), dX(9 * NP), V(3 * NP);
   auto ijk = [&](int node, int m) { return (node / stride[m]) % n; };
   // d f / d xi_m at `node` for a nodal field f of one element
   auto deriv = [&](const double* f, int m, int node) {
@@ -397,9 +397,18 @@ static bool build_curv(const dg_desc& d, const Ctx& c, const MeshBuild& mb, std:
       warp_point(d, xc, xw);
       for (int q = 0; q < dim; ++q) X[q * NP + node] = xw[q];
     }
+    // The metrics are formed from coordinates relative to the element's first
+    // node (Xl): derivatives of a constant vanish and so does the curl of a
+    // constant times a gradient, so this changes nothing in exact arithmetic,
+    // but the rounding becomes relative to the element's size rather than to
+    // its distance from the origin.
+    for (int q = 0; q < dim; ++q) {
+      const double x0 = X[q * NP];
+      for (int node = 0; node < NP; ++node) Xl[q * NP + node] = X[q * NP + node] - x0;
+    }
     for (int q = 0; q < dim; ++q)
       for (int m = 0; m < dim; ++m)
-        for (int node = 0; node < NP; ++node) dX[(q * 3 + m) * NP + node] = deriv(&X[q * NP], m, node);
+        for (int node = 0; node < NP; ++node) dX[(q * 3 + m) * NP + node] = deriv(&Xl[q * NP], m, node);
     for (int node = 0; node < NP; ++node) {
       double Ja[3][3] = {{0.0}}, J;
       auto dx = [&](int q, int m) { return dX[(q * 3 + m) * NP + node]; };
@@ -426,7 +435,7 @@ static bool build_curv(const dg_desc& d, const Ctx& c, const MeshBuild& mb, std:
       for (int nn = 0; nn < 3; ++nn) {
         const int mm = (nn + 1) % 3, ll = (nn + 2) % 3;
         for (int k = 0; k < 3; ++k)
-          for (int node = 0; node < NP; ++node) V[k * NP + node] = X[ll * NP + node] * dX[(mm * 3 + k) * NP + node];
+          for (int node = 0; node < NP; ++node) V[k * NP + node] = Xl[ll * NP + node] * dX[(mm * 3 + k) * NP + node];
         for (int node = 0; node < NP; ++node)
           for (int i = 0; i < 3; ++i) {
             const double curl = deriv(&V[((i + 2) % 3) * NP], (i + 1) % 3, node) -

@@ -97,3 +97,79 @@ def rel_err_floor(got, ref, floor):
     num = (g - r).abs().amax(dim=1)
     den = torch.maximum(r.abs().amax(dim=1), floor.to(r.dtype))
     return float((num / den).max())
+
+
+def mirror(U, nel, dirs, mom=1):
+    """Mirror image of a state on a lexicographic (x fastest) element grid:
+    reverse the element and node order along each direction in `dirs` and
+    negate those momentum components.  L(mirror(U)) = mirror(L(U)) in exact
+    arithmetic whenever the mesh is invariant under the mirror (any periodic
+    Cartesian box for one direction; the warped meshes for pairs of
+    directions, a half turn), while every derivative sum and every interface
+    flux is evaluated in reversed order."""
+    B, nv, E = U.shape[:3]
+    dim = len(nel)
+    n = U.shape[-1]
+    X = U.reshape((B, nv) + tuple(reversed(nel)) + (n,) * dim).clone()
+    for l in dirs:
+        X = X.flip(2 + dim - 1 - l).flip(2 + dim + dim - 1 - l)
+        X[:, mom + l] = -X[:, mom + l]
+    return X.reshape(U.shape)
+
+
+def cycle(U, nel, mom=1):
+    """Relabel the axes of a 3-D state on a cube of equal element counts,
+    (x, y, z) -> (y, z, x): the arrays are transposed and the momentum
+    components permuted with them.  L(cycle(U)) = cycle(L(U)) in exact
+    arithmetic; the derivative sums then run along other memory axes."""
+    assert len(nel) == 3 and nel[0] == nel[1] == nel[2]
+    B, nv, E = U.shape[:3]
+    n = U.shape[-1]
+    X = U.reshape((B, nv) + tuple(reversed(nel)) + (n,) * 3)
+    X = X.permute(0, 1, 4, 2, 3, 7, 5, 6)
+    idx = list(range(nv))
+    idx[mom:mom + 3] = [mom + 1, mom + 2, mom]
+    return X[:, idx].reshape(U.shape).contiguous()
+
+
+def rounding_spread(rhs, U, nel, mirrors, cycles=False):
+    """Per-variable rounding spread of the oracle's own FP64 arithmetic at U:
+    the largest |L(U) - mirror(L(mirror(U)))| over the mirror images in
+    `mirrors` (and, with cycles=True on a cube, over the two cyclic
+    relabellings of the axes).  The mirrored evaluation sees the same input bits (so the same
+    interface jumps) but forms every derivative sum and every interface flux
+    in reversed order: the difference is what two correct FP64 evaluations of
+    L differ by at this state, the floor below which a parity comparison
+    cannot see.  Returns (L(U), spread)."""
+    R = rhs(U)
+    B, nv = R.shape[:2]
+    s = torch.zeros(nv, dtype=torch.float64)
+    cands = [lambda X, d=d: mirror(X, nel, d) for d in mirrors]
+    inv = [lambda X, d=d: mirror(X, nel, d) for d in mirrors]
+    if cycles:
+        cands += [lambda X: cycle(X, nel), lambda X: cycle(cycle(X, nel), nel)]
+        inv += [lambda X: cycle(cycle(X, nel), nel), lambda X: cycle(X, nel)]
+    for f, g in zip(cands, inv):
+        C = g(rhs(f(U)))
+        s = torch.maximum(s, (C - R).reshape(B, nv, -1).transpose(0, 1).reshape(nv, -1).abs().amax(dim=1))
+    return R, s
+
+
+# Parity bound where cancellation sets the floor: per variable
+#   ||got_v - ref_v||_inf <= max(1e-12 ||ref_v||_inf, SPREAD_FACTOR * spread_v).
+# The library forms reciprocals to within 11 units in the last place (the
+# oracle divides, 0.5) and sums in a different order, so its own rounding
+# error can be up to about 10 times the oracle's; the difference of the two is
+# then within about 11 spreads, and the factor 16 leaves headroom on that.
+SPREAD_FACTOR = 16.0
+
+
+def spread_err(got, ref, spread, rel=1e-12):
+    """max over variables of ||got_v - ref_v||_inf / max(rel ||ref_v||_inf,
+    SPREAD_FACTOR spread_v): below 1 passes."""
+    B, nv = ref.shape[:2]
+    g = got.reshape(B, nv, -1).transpose(0, 1).reshape(nv, -1)
+    r = ref.reshape(B, nv, -1).transpose(0, 1).reshape(nv, -1)
+    num = (g - r).abs().amax(dim=1)
+    den = torch.maximum(rel * r.abs().amax(dim=1), SPREAD_FACTOR * spread.to(r.dtype)).clamp_min(1e-300)
+    return float((num / den).max())
