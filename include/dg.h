@@ -289,6 +289,19 @@ int dg_dt_cfl(dg_ctx* ctx, const void* U, double cfl, double* dt, void* stream);
  * out is host memory of B*(nv+1) doubles.  Synchronises. */
 int dg_integrals(dg_ctx* ctx, const void* U, double* out, void* stream);
 
+/* Allocation-free variant of dg_integrals, for callers that cannot allocate
+ * device memory during the call (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same kernels and the same sums
+ * in the same order, with the partial sums kept in one fixed device array per
+ * GPU (2 MiB, held until the process ends) instead of the context's scratch.
+ * out is DEVICE memory of B*(nv+1) doubles, caller-owned, written
+ * asynchronously on `stream` (the call neither copies to the host nor
+ * synchronises) in the layout of dg_integrals.  Calls no allocating routine.
+ * Every call on one GPU shares the fixed array: calls that overlap on one GPU
+ * (from any context, stream or thread) race.  Returns DG_ERR_UNSUPPORTED when
+ * batch * (nvars + 1) exceeds 512, DG_ERR_ARG for null pointers. */
+int dg_integrals_noalloc(dg_ctx* ctx, const void* U, double* out, void* stream);
+
 /* Read (and optionally reset) the sticky counters.  Synchronises. */
 int dg_status_read(dg_ctx* ctx, dg_counters* out, int32_t reset, void* stream);
 

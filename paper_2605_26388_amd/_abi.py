@@ -24,7 +24,7 @@ EXPORTS = (
     "dg_create", "dg_destroy", "dg_sizes", "dg_node_coords", "dg_rhs", "dg_rk_stage", "dg_rk_stage_dual",
     "dg_ssprk54_step",
     "dg_source_chem", "dg_rhs_adjoint", "dg_rk_stage_adjoint", "dg_dt_cfl", "dg_integrals",
-    "dg_status_read", "dg_strerror", "dg_last_error",
+    "dg_integrals_noalloc", "dg_status_read", "dg_strerror", "dg_last_error",
 )
 
 
@@ -104,6 +104,7 @@ def load():
         "dg_rk_stage_adjoint": (c_int32, [P, P, P, P, P, c_double, c_double, c_double, c_int32, P]),
         "dg_dt_cfl": (c_int32, [P, P, c_double, POINTER(c_double), P]),
         "dg_integrals": (c_int32, [P, P, POINTER(c_double), P]),
+        "dg_integrals_noalloc": (c_int32, [P, P, P, P]),
         "dg_status_read": (c_int32, [P, POINTER(Counters), c_int32, P]),
         "dg_strerror": (ctypes.c_char_p, [c_int32]),
         "dg_last_error": (ctypes.c_char_p, []),

@@ -670,7 +670,13 @@ int dg_create(const dg_desc* desc, dg_ctx** out) {
   }
 
   DeviceGuard guard(c.device);
-  hipError_t e = hipSuccess;
+  // device address of the allocation-free entry point's fixed scratch array
+  // (looked up once per device, with the device current)
+  hipError_t e = noalloc_scratch_init(c.device);
+  if (e != hipSuccess) {
+    delete ctx;
+    return hip_fail(e, "dg_create scratch symbol");
+  }
   const size_t red_cap = (size_t)std::max(c.B, 1) * 512 * 10 + 1024;
   if ((e = upload(&c.d_nbr, mb.nbr.data(), mb.nbr.size() * sizeof(int))) != hipSuccess ||
       (e = upload(&c.d_geo, mb.geo.data(), mb.geo.size() * sizeof(double))) != hipSuccess ||
@@ -941,6 +947,19 @@ int dg_integrals(dg_ctx* ctx, const void* U, double* out, void* stream) {
     e = hipMemcpyAsync(out, c.d_red_out, (size_t)c.B * (c.nv + 1) * sizeof(double), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   return e == hipSuccess ? DG_OK : hip_fail(e, "dg_integrals");
+}
+
+int dg_integrals_noalloc(dg_ctx* ctx, const void* U, double* out, void* stream) {
+  if (!ctx || !U || !out) return fail(DG_ERR_ARG, "dg_integrals_noalloc: null argument");
+  Ctx& c = ctx->c;
+  if (c.nv + 1 > 10) return fail(DG_ERR_UNSUPPORTED, "dg_integrals_noalloc: too many variables");
+  if (noalloc_integrals_need(c) > NOALLOC_SCRATCH_DOUBLES)
+    return fail(DG_ERR_UNSUPPORTED, "dg_integrals_noalloc: batch * (nvars + 1) = " +
+                                        std::to_string(c.B * (c.nv + 1)) + " exceeds the fixed scratch limit of " +
+                                        std::to_string(NOALLOC_SCRATCH_DOUBLES / 512));
+  DeviceGuard guard(c.device);
+  const hipError_t e = launch_integrals_noalloc(c, U, out, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DG_OK : hip_fail(e, "dg_integrals_noalloc");
 }
 
 int dg_status_read(dg_ctx* ctx, dg_counters* out, int32_t reset, void* stream) {

@@ -119,6 +119,12 @@ hipError_t launch_stage(const Ctx& c, const StageParams& sp, hipStream_t s);
 hipError_t launch_mortar(const Ctx& c, const void* U, hipStream_t s);
 hipError_t launch_coords(const Ctx& c, const double* corner, double* xyz, hipStream_t s);
 hipError_t launch_integrals(const Ctx& c, const void* U, double* d_out, hipStream_t s);
+// allocation-free integrals: partials in a fixed per-GPU device array of
+// NOALLOC_SCRATCH_DOUBLES doubles whose address is looked up once per device
+constexpr size_t NOALLOC_SCRATCH_DOUBLES = (size_t)1 << 18;  // 2 MiB
+hipError_t noalloc_scratch_init(int device);                  // with `device` current
+size_t noalloc_integrals_need(const Ctx& c);                   // doubles of scratch one call uses
+hipError_t launch_integrals_noalloc(const Ctx& c, const void* U, double* d_out, hipStream_t s);
 hipError_t launch_lam_max(const Ctx& c, const void* U, double* d_out, hipStream_t s);
 hipError_t launch_source(const Ctx& c, const void* U, void* out, double h, int mode, hipStream_t s);
 hipError_t launch_ns(const Ctx& c, const StageParams& sp, hipStream_t s);

@@ -4,6 +4,8 @@
 // Reductions are deterministic: every block writes its partial in a fixed
 // order (wave shuffles, then LDS across waves), and a second single-block pass
 // adds the partials in index order.  No atomics.
+#include <mutex>
+
 #include "dg_device.hpp"
 
 namespace dg {
@@ -104,19 +106,66 @@ k_final_sum(const double* partial, int nparts, int nq, double* out) {
     for (int q = 0; q < nq; ++q) out[(size_t)b * nq + q] = x[q];
 }
 
-hipError_t launch_integrals(const Ctx& c, const void* U, double* d_out, hipStream_t s) {
+// Both passes of the integrals with the partials in `partial` (B x
+// RED_BLOCKS x (nv + 1) doubles, every one written before it is read).
+static hipError_t integrals_into(const Ctx& c, const void* U, double* partial, double* d_out, hipStream_t s) {
   const int nspec = is_reacting(c.desc.physics) ? c.mech.nspecies : 1;
   dim3 grid(RED_BLOCKS, c.B);
   if (c.desc.precision == DG_F32)
     hipLaunchKernelGGL((k_integrals<float>), grid, dim3(RED_BS), 0, s, static_cast<const float*>(U), c.dim, c.n,
-                       c.E, c.nv, nspec, c.d_geo, c.curv ? c.d_met : nullptr, c.d_K, c.d_red);
+                       c.E, c.nv, nspec, c.d_geo, c.curv ? c.d_met : nullptr, c.d_K, partial);
   else
     hipLaunchKernelGGL((k_integrals<double>), grid, dim3(RED_BS), 0, s, static_cast<const double*>(U), c.dim, c.n,
-                       c.E, c.nv, nspec, c.d_geo, c.curv ? c.d_met : nullptr, c.d_K, c.d_red);
+                       c.E, c.nv, nspec, c.d_geo, c.curv ? c.d_met : nullptr, c.d_K, partial);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_final_sum, dim3(c.B), dim3(RED_BS), 0, s, c.d_red, RED_BLOCKS, c.nv + 1, d_out);
+  hipLaunchKernelGGL(k_final_sum, dim3(c.B), dim3(RED_BS), 0, s, partial, RED_BLOCKS, c.nv + 1, d_out);
   return hipGetLastError();
+}
+
+hipError_t launch_integrals(const Ctx& c, const void* U, double* d_out, hipStream_t s) {
+  return integrals_into(c, U, c.d_red, d_out, s);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free integrals.  The partials live in one fixed device array per
+// GPU (file scope, zero-initialised at load, held until the process ends)
+// instead of the context's scratch.  In host code `scratch` only names the
+// symbol; its device address is looked up once per device, with that device
+// current, and only that address is ever handed to a kernel.  Every call on a
+// GPU shares the array: calls that overlap on one GPU (two streams, two
+// threads) race.  Nothing in it needs clearing: the first pass writes every
+// partial the second pass reads.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device) {
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = static_cast<double*>(p);
+  return hipSuccess;
+}
+
+size_t noalloc_integrals_need(const Ctx& c) { return (size_t)c.B * RED_BLOCKS * (size_t)(c.nv + 1); }
+
+hipError_t launch_integrals_noalloc(const Ctx& c, const void* U, double* d_out, hipStream_t s) {
+  double* p = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (c.device >= 0 && c.device < NOALLOC_MAX_DEVICES) p = g_scratch_ptr[c.device];
+  }
+  if (!p) return hipErrorNotInitialized;
+  return integrals_into(c, U, p, d_out, s);
 }
 
 // Maxima of |u| + a and of 1/rho over all nodes and batch members.

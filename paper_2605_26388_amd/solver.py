@@ -210,6 +210,16 @@ class Solver:
         check(self.lib.dg_integrals(self._ctx, self._ptr(U, "U"), out, _stream(self.device)), "dg_integrals")
         return np.array(out[:]).reshape(self.batch, self.nv + 1)
 
+    def integrals_noalloc(self, U, out):
+        """dg_integrals_noalloc: integrals into the device tensor `out`
+        (float64, [batch, nv + 1]) on the current stream, no host copy."""
+        if out.dtype != torch.float64 or out.device != self.device or not out.is_contiguous() \
+                or out.numel() != self.batch * (self.nv + 1):
+            raise ValueError("out must be a contiguous float64 device tensor of batch * (nv + 1) values")
+        check(self.lib.dg_integrals_noalloc(self._ctx, self._ptr(U, "U"), ctypes.c_void_p(out.data_ptr()),
+                                            _stream(self.device)), "dg_integrals_noalloc")
+        return out
+
     def status(self, reset=False):
         c = _abi.Counters()
         check(self.lib.dg_status_read(self._ctx, ctypes.byref(c), int(bool(reset)), _stream(self.device)),
