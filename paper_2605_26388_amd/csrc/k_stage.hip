@@ -50,8 +50,19 @@ template <> __device__ __forceinline__ float dmat_entry<float>(const RefConsts* 
 // relative error of about 1e-7 stays far below the form's stated accuracy.
 template <class PHYS, bool F32>
 __device__ __forceinline__ double wave_sound(const Thermo& t) {
-  if constexpr (F32) return static_cast<double>(__builtin_amdgcn_sqrtf(static_cast<float>(t.k * t.p * t.ri)));
-  else return sound<PHYS>(t);
+  if constexpr (F32) {
+    return static_cast<double>(__builtin_amdgcn_sqrtf(static_cast<float>(t.k * t.p * t.ri)));
+  } else {
+    // The FP64 form: the hardware reciprocal square root refined by one
+    // coupled Goldschmidt step, relative error about 1.5 e^2 for an estimate
+    // error e of about 2^-23, i.e. near 1e-14 -- the coefficient only scales
+    // the jump term, and both elements of a face evaluate it on the same
+    // operands, so they still agree to the bit.
+    const double x = t.k * t.p * t.ri;
+    const double y = __builtin_amdgcn_rsq(x);
+    const double g = x * y, h = 0.5 * y;
+    return fma(g, fma(-g, h, 0.5), g);
+  }
 }
 
 // Logarithmic mean {{x}}_ln = (x - y) / (ln x - ln y) of positive x, y and its
@@ -302,13 +313,18 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
   __shared__ double sQ[SPLIT ? DIM + 5 : 1][SPLIT ? EPB * NP : 1];  // rho, v, p, rho/p, their logs
   __shared__ int sFar;  // split form: some lane of the block needs the exact log means
   __shared__ DT sD[n * n];
+  // One element per workgroup: D scaled by -2/h_l for each direction, so the
+  // volume sweep accumulates straight into dU/dt (no per-direction rescale).
+  constexpr bool DSCALED = (EPB == 1) && !SPLIT;
+  __shared__ T sDg[DSCALED ? DIM : 1][DSCALED ? n * n : 1];
   __shared__ double sRef[(F32 && !SPLIT) ? EPB : 1][DIM][NV];
 
   const int tid = threadIdx.x;
   // the lane's entry of D, stored to LDS only just before the first barrier
   // (no wait on this load ahead of the state loads)
   static_assert(n * n <= S::BS, "one D entry per lane");
-  const DT dval = tid < n * n ? dmat_entry<DT>(mv.K, tid) : DT(0);
+  const DT dval = (!DSCALED && tid < n * n) ? dmat_entry<DT>(mv.K, tid) : DT(0);
+  const double dsc = (DSCALED && tid < n * n) ? mv.K->D[tid] : 0.0;
 
   const int E = mv.E;
   const int nEB = (E + EPB - 1) / EPB;
@@ -393,7 +409,13 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
   for (int d = 0; d < DIM; ++d) vel[d] = u[MOM + d] * th.ri;
 
   // ---- stage physical fluxes (split form: primitives) in LDS -------------
-  if (tid < n * n) sD[tid] = dval;
+  if (!DSCALED && tid < n * n) sD[tid] = dval;
+  if constexpr (DSCALED) {
+    if (tid < n * n) {
+#pragma unroll
+      for (int l = 0; l < DIM; ++l) sDg[l][tid] = static_cast<T>(-g[l] * dsc);
+    }
+  }
   SplitNode<DIM> own;
   if constexpr (SPLIT) {
     own.hr = 0.5 * u[0];
@@ -477,13 +499,18 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
       const int base = tid - il * st;
       T drow[n];
 #pragma unroll
-      for (int m = 0; m < n; ++m) drow[m] = sD[il * n + m];
+      for (int m = 0; m < n; ++m) drow[m] = DSCALED ? sDg[DSCALED ? l : 0][il * n + m] : sD[il * n + m];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        T s = 0;
+        if constexpr (DSCALED) {
 #pragma unroll
-        for (int m = 0; m < n; ++m) s = fma(drow[m], sF[l][v][base + m * st], s);
-        acc[v] = fma(AT(-g[l]), static_cast<AT>(s), acc[v]);
+          for (int m = 0; m < n; ++m) acc[v] = fma(AT(drow[m]), AT(sF[l][v][base + m * st]), acc[v]);
+        } else {
+          T s = 0;
+#pragma unroll
+          for (int m = 0; m < n; ++m) s = fma(drow[m], sF[l][v][base + m * st], s);
+          acc[v] = fma(AT(-g[l]), static_cast<AT>(s), acc[v]);
+        }
       }
     }
   }
@@ -513,7 +540,7 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
     PHYS::flux(un[l], vn, tn.p, l, Fn);
     const double co = fabs(vel[l]) + aown;
     const double cn = fabs(vn) + wave_sound<PHYS, F32>(tn);
-    const double lam = co >= cn ? co : cn;
+    const double lam = fmax(co, cn);
     const double sgn = side[l] == 1 ? 1.0 : -1.0;  // +1 on the +xi_l face
     const double hs = sgn * lam;
 #pragma unroll
@@ -580,6 +607,183 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
           Buf<T>::store(r2, off, w, v * pstride);
         }
       }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The headline shape -- 3-D, N = 3 (64 nodes: one element per single-wave
+// workgroup), conforming faces, FP64 -- with every global read of the stage
+// issued at the start, so that a wave waits for memory once instead of three
+// times (own state, then neighbour face nodes, then U0):
+//   * U_k of the element's own nodes into registers (coalesced);
+//   * the neighbour face nodes of all three directions straight into LDS by
+//     buffer-to-LDS loads (no registers held): per direction and variable
+//     one 4-byte load per lane, lane L fetching dword L & 1 of face slot
+//     L >> 1 (slots 0-15 the -xi_l face, 16-31 the +xi_l face, tangential
+//     index a + 4 b in the two other directions);
+//   * U0, when the stage reads it, into LDS by 16-byte loads (two variables
+//     per instruction).
+// The directions are then processed one after the other: the flux along l
+// is staged in LDS, swept with D (scaled by -2/h_l), and the lanes on an l
+// face apply their interface correction with the own flux still in
+// registers.  Being one wave, the workgroup needs no barrier: LDS accesses of
+// a wave complete in order, and a wave-level fence keeps the compiler from
+// reordering them.  Same arithmetic per term as k_stage.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+#define DG_LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
+
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
+k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
+  using PHYS = EulerPhys<3>;
+  constexpr int DIM = 3, N = 3, n = 4, NP = 64, NV = 5;
+  __shared__ double sF[NV][NP];
+  __shared__ double sDg[DIM][n * n];
+  __shared__ __attribute__((aligned(16))) unsigned sNb[DIM][NV][64];  // [l][v][2 * slot + half]
+  __shared__ __attribute__((aligned(16))) double sU0[NV + 1][NP];  // spare row: see the U0 loads below
+
+  const int tid = threadIdx.x;
+  const double dsc = tid < n * n ? mv.K->D[tid] : 0.0;
+  const int E = mv.E;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = blk / E;
+  const int e = zfast_block<1>(blk - b * E, mv);
+  const int ec = wave_uniform(e);
+  const int* nb = mv.nbr + (size_t)ec * 2 * DIM;
+  int nbl[2 * DIM];
+#pragma unroll
+  for (int q = 0; q < 2 * DIM; ++q) nbl[q] = nb[q];
+  double g[DIM];
+#pragma unroll
+  for (int l = 0; l < DIM; ++l) g[l] = mv.geo[(size_t)ec * 4 + l];
+  const double hwinv = 0.5 * mv.K->wend_inv;
+  const int ii[3] = {tid & 3, (tid >> 2) & 3, tid >> 4};
+  const int stride[3] = {1, 4, 16};
+
+  const size_t plane = (size_t)E * NP;
+  const size_t abytes = (size_t)NV * plane * sizeof(double);
+  const unsigned pstride = (unsigned)(plane * sizeof(double));
+  const rsrc_t rU = make_rsrc(static_cast<const double*>(sp.Uk) + (size_t)b * NV * plane, abytes);
+  const unsigned off = (unsigned)(ec * NP + tid);
+
+  // own state into registers
+  double u[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u[v] = Buf<double>::load(rU, off, v * pstride);
+  // neighbour face nodes into LDS
+  {
+    const int slot = tid >> 1, half = tid & 1, side = slot >> 4, ta = slot & 3, tb = (slot >> 2) & 3;
+#pragma unroll
+    for (int l = 0; l < DIM; ++l) {
+      const int o1 = l == 0 ? 1 : 0, o2 = l == 2 ? 1 : 2;
+      const int ne = side ? nbl[2 * l + 1] : nbl[2 * l];
+      const int node = (side ? 0 : N) * stride[l] + ta * stride[o1] + tb * stride[o2];
+      const unsigned voff = (unsigned)(ne * NP + node) * 8u + 4u * (unsigned)half;
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rU, DG_LDS_PTR(&sNb[l][v][0]), 4, voff, v * pstride, 0, 0);
+    }
+  }
+  const bool use_u0 = (sp.mode != 0) && (sp.a != 0.0);
+  if (use_u0) {
+    const rsrc_t r0 = make_rsrc(static_cast<const double*>(sp.U0) + (size_t)b * NV * plane, abytes);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int v = 2 * q + (tid >> 5);
+      if (v < NV) {
+        const unsigned voff = (unsigned)v * pstride + (unsigned)(ec * NP + 2 * (tid & 31)) * 8u;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r0, DG_LDS_PTR(&sU0[2 * q][0]), 16, voff, 0, 0, 0);
+      }
+    }
+  }
+
+  Thermo th;
+  const bool ok = PHYS::thermo(u, th, pc);
+  if (!ok) report_nonphysical(mv.counters, mv.first_bad, ((unsigned long long)b * E + e) * NP + tid);
+  double vel[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) vel[d] = u[1 + d] * th.ri;
+  const double aown = wave_sound<PHYS, false>(th);
+  if (tid < n * n) {
+#pragma unroll
+    for (int l = 0; l < DIM; ++l) sDg[l][tid] = -g[l] * dsc;
+  }
+
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+#pragma unroll
+  for (int l = 0; l < DIM; ++l) {
+    double F[NV];
+    PHYS::flux(u, vel[l], th.p, l, F);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sF[v][tid] = F[v];
+    wave_lds_fence();
+    // volume integral along l
+    const int il = ii[l], st = stride[l], base = tid - il * st;
+    double drow[n];
+#pragma unroll
+    for (int m = 0; m < n; ++m) drow[m] = sDg[l][il * n + m];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int m = 0; m < n; ++m) acc[v] = fma(drow[m], sF[v][base + m * st], acc[v]);
+    // surface correction on the l faces: 2 (F* - F_own) = (F_nb - F_own) - s lam (U_nb - U_own)
+    const int side = (il == 0) ? 0 : ((il == N) ? 1 : -1);
+    if (side >= 0) {
+      const int o1 = l == 0 ? 1 : 0, o2 = l == 2 ? 1 : 2;
+      const int slot = side * 16 + ii[o1] + 4 * ii[o2];
+      double un[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) un[v] = *reinterpret_cast<const double*>(&sNb[l][v][2 * slot]);
+      Thermo tn;
+      PHYS::thermo(un, tn, pc);
+      const double vn = un[1 + l] * tn.ri;
+      double Fn[NV];
+      PHYS::flux(un, vn, tn.p, l, Fn);
+      const double co = fabs(vel[l]) + aown;
+      const double cn = fabs(vn) + wave_sound<PHYS, false>(tn);
+      const double lam = fmax(co, cn);
+      const double sgn = side == 1 ? 1.0 : -1.0;
+      const double hs = sgn * lam;
+      const double sc = -sgn * (g[l] * hwinv);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[v] = fma(sc, fma(-hs, un[v] - u[v], Fn[v] - F[v]), acc[v]);
+    }
+    wave_lds_fence();  // the next direction overwrites sF
+  }
+
+  // ---- output ----------------------------------------------------------------
+  const rsrc_t ro = make_rsrc(static_cast<double*>(sp.out) + (size_t)b * NV * plane, abytes);
+  if (sp.mode == 0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Buf<double>::store(ro, off, acc[v], v * pstride);
+    return;
+  }
+  double r[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    r[v] = fma(sp.c, acc[v], sp.b * u[v]);
+    if (use_u0) r[v] = fma(sp.a, sU0[v][tid], r[v]);
+  }
+  if (sp.rho_min > 0.0 || sp.p_min > 0.0) positivity_floor(r, sp.rho_min, sp.p_min, 1.0 / (pc.gamma - 1.0), mv.counters);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) Buf<double>::store(ro, off, r[v], v * pstride);
+  if (sp.mode == 2) {  // second combination of the same L(Uk), no floor
+    const rsrc_t r2 = make_rsrc(static_cast<double*>(sp.out2) + (size_t)b * NV * plane, abytes);
+    const bool use_v = sp.a2 != 0.0;
+    const rsrc_t rv = make_rsrc(static_cast<const double*>(use_v ? sp.V : sp.Uk) + (size_t)b * NV * plane, abytes);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double w = fma(sp.c2, acc[v], sp.b2 * u[v]);
+      if (use_v) w = fma(sp.a2, Buf<double>::load(rv, off, v * pstride), w);
+      Buf<double>::store(r2, off, w, v * pstride);
     }
   }
 }
@@ -656,6 +860,11 @@ static hipError_t go(const Ctx& c, const StageParams& sp, hipStream_t s) {
   using SH = Shape<DIM, N>;
   const int nEB = (c.E + SH::EPB - 1) / SH::EPB;
   const int nblk = nEB * c.B;
+  if constexpr (DIM == 3 && N == 3 && std::is_same<PHYS, EulerPhys<3>>::value && std::is_same<T, double>::value &&
+                !MORTAR && !SPLIT) {
+    hipLaunchKernelGGL(k_stage_n3, dim3(nblk), dim3(64), 0, s, sp, mesh_view(c), c.pc);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL((k_stage<DIM, N, PHYS, T, MORTAR, SPLIT>), dim3(nblk), dim3(SH::BS), 0, s, sp, mesh_view(c),
                      c.pc);
   return hipGetLastError();
