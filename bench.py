@@ -74,27 +74,49 @@ def warm_up(solver, U, dt, steps, t1, t2, block=100):
     del W
 
 
-def time_stages(solver, U, dt, steps, warmup):
+def time_stages(solver, U, dt, steps, warmup, steady=False):
     """Run warmup + timed SSP-RK3 steps; returns (wall seconds of the timed
     steps, mean duration of one dg_rk_stage launch in seconds).  The timed
     steps run back to back (no host work or markers between the launches);
     one pair of HIP events on the launch stream brackets them, so the mean
     launch duration is the GPU time of the timed region over its 3K launches
-    (consecutive dependent launches start as the previous one retires)."""
+    (consecutive dependent launches start as the previous one retires).
+    With steady=True, after that measurement a further >= 0.2 s of untimed
+    steps bring the device to the clock it sustains under this load, and
+    the same number of steps is timed again: the third value returned (None
+    otherwise) is that steady-state mean launch duration, reported beside
+    the headline, never as it."""
     t1 = solver.empty()
     t2 = solver.empty()
     stream = torch.cuda.current_stream()
+    U0 = U.clone()
     warm_up(solver, U, dt, warmup, t1, t2)
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    a.record(stream)
-    for _ in range(steps):
-        solver.ssprk3_step(U, dt, t1, t2)
-    b.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kern = a.elapsed_time(b) * 1e-3 / (3 * steps)
-    return wall, kern
+
+    def timed():
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        a.record(stream)
+        for _ in range(steps):
+            solver.ssprk3_step(U, dt, t1, t2)
+        b.record(stream)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, a.elapsed_time(b) * 1e-3 / (3 * steps)
+
+    wall, kern = timed()
+    kern_steady = None
+    if steady:
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < 0.2:
+            if k % 100 == 0:
+                U.copy_(U0)
+            solver.ssprk3_step(U, dt, t1, t2)
+            k += 1
+            if k % 50 == 0:
+                torch.cuda.synchronize()
+        U.copy_(U0)
+        _, kern_steady = timed()
+    return wall, kern, kern_steady
 
 
 def time_adjoint(solver, U, dt, steps, warmup):
@@ -158,9 +180,21 @@ def cpu_baseline(p, budget_s=15.0):
     single = dof / (time.perf_counter() - t1)
     torch.set_num_threads(threads)
     return dict(value=dof * nstage / el, unit="DOF-updates/s per RK stage", cores=threads,
-                kind="oracle", single_thread_value=single,
+                kind="oracle", single_thread_value=single, cpu_model=cpu_model(),
                 sample=f"{nstage} full RK stages of the 32^3 N=3 mesh ({dof} DOF) in {el:.1f} s, "
-                f"torch-CPU float64 on {threads} threads ({platform.machine()}); plus one stage on 1 thread")
+                f"torch-CPU float64 on {threads} threads of {cpu_model()}; plus one stage on 1 thread")
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), else the machine type."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.machine()
 
 
 def kernel_source_hash():
@@ -178,7 +212,7 @@ def measured_traffic(bytes_per_launch):
     summary (FETCH_SIZE / WRITE_SIZE KiB per dispatch, scaled by the factors a
     plain device copy of known size gives); None when the kernel sources have
     changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "k_stage_euler3d_f64_counters.json")
+    path = os.path.join(ROOT, "profiles", "k_stage_n3_euler3d_f64_counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -213,6 +247,48 @@ def time_calls(fn, reps, warmup=2, settle_s=0.05, reset=None):
         fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / reps
+
+
+def steady_summary(res, note):
+    f64, f32 = res["f64"], res["f32"]
+    if f64["kern_steady"] is None or f32["kern_steady"] is None:
+        return None
+    return {"f64_kernel_us": f64["kern_steady"] * 1e6, "f32_kernel_us": f32["kern_steady"] * 1e6,
+            "f64_roofline_frac": f64["bytes"] / f64["kern_steady"] / 1e9 / HBM_PEAK_GBS,
+            "fp32_speedup_vs_fp64": f64["kern_steady"] / f32["kern_steady"], "note": note}
+
+
+def bench_large(steps, warmup):
+    """The same stage at 64^3 (671 MB per FP64 state array, past the 256 MB
+    last-level cache), FP64 and FP32, same protocol as the headline (the
+    seeded state is evaluated on the device)."""
+    from paper_2605_26388_amd import Solver
+    p = di.PRESETS["euler3d_L"]
+    res = {}
+    for prec in ("f64", "f32"):
+        s = Solver(3, p["N"], p["nel"], p["lo"], p["hi"], precision=prec)
+        X = s.node_coords()
+        U = di.random_euler(X, p["lo"], p["hi"])[None].to(s.dtype).contiguous()
+        del X
+        dt = s.dt_cfl(U, p["cfl"])
+        dof = s.E * s.Np * s.nv
+        wall, kern, kern_steady = time_stages(s, U, dt, steps, warmup, steady=True)
+        st = s.status()
+        assert st["nonphysical"] == 0, st
+        byt = WORDS_PER_DOF_STAGE * (8 if prec == "f64" else 4) * dof
+        res[prec] = {"kernel_us": kern * 1e6, "value": dof * 3 * steps / wall, "bytes_per_launch": byt,
+                     "roofline_frac": byt / kern / 1e9 / HBM_PEAK_GBS,
+                     "steady_kernel_us": kern_steady * 1e6,
+                     "steady_roofline_frac": byt / kern_steady / 1e9 / HBM_PEAK_GBS}
+        log(f"64^3 {prec}: kernel {kern * 1e6:.1f} us/launch ({res[prec]['roofline_frac']:.3f} of HBM), "
+            f"steady {kern_steady * 1e6:.1f} us")
+        del U
+        s.close()
+        torch.cuda.empty_cache()
+    res["fp32_speedup_vs_fp64"] = res["f64"]["kernel_us"] / res["f32"]["kernel_us"]
+    res["workload"] = ("euler3d_L: 3-D Euler 64^3 hex elements, N=3 (83.9M DOF), smooth random state, "
+                       "SSP-RK3 at CFL 0.5")
+    return res
 
 
 def bench_navier_stokes(reps, nel=None):
@@ -275,7 +351,7 @@ def bench_split(steps, warmup):
         X = s.node_coords().cpu().numpy()
         U = torch.tensor(di.random_euler(X, p["lo"], p["hi"]))[None].to(s.device, s.dtype).contiguous()
         dt = s.dt_cfl(U, p["cfl"])
-        wall, kern = time_stages(s, U, dt, steps, warmup)
+        wall, kern, _ = time_stages(s, U, dt, steps, warmup)
         st = s.status()
         assert st["nonphysical"] == 0, st
         dof = s.E * s.Np * s.nv
@@ -380,7 +456,7 @@ def bench_curvilinear(steps, warmup):
     X = s.node_coords().cpu().numpy()
     U = torch.tensor(di.random_euler(X, p["lo"], p["hi"]))[None].to(s.device).contiguous()
     dt = s.dt_cfl(U, p["cfl"])
-    wall, kern = time_stages(s, U, dt, steps, warmup)
+    wall, kern, _ = time_stages(s, U, dt, steps, warmup)
     st = s.status()
     assert st["nonphysical"] == 0, st
     nodes = s.E * s.Np
@@ -471,15 +547,14 @@ def main():
     for form in forms:
         prec = form
         s = Solver(3, p["N"], p["nel"], p["lo"], p["hi"], precision=prec)
-        X = s.node_coords().cpu().numpy()
-        U = torch.tensor(di.random_euler(X, p["lo"], p["hi"]))[None].to(s.device, s.dtype).contiguous()
+        U = di.random_euler(s.node_coords(), p["lo"], p["hi"])[None].to(s.dtype).contiguous()
         dt = s.dt_cfl(U, p["cfl"])
         dof = s.E * s.Np * s.nv
-        wall, kern = time_stages(s, U, dt, args.steps, args.warmup)
+        wall, kern, kern_steady = time_stages(s, U, dt, args.steps, args.warmup, steady=not args.only)
         st = s.status()
         assert st["nonphysical"] == 0, st
         bytes_per_launch = WORDS_PER_DOF_STAGE * (8 if prec == "f64" else 4) * dof
-        res[form] = dict(wall=wall, kern=kern, dof=dof, bytes=bytes_per_launch,
+        res[form] = dict(wall=wall, kern=kern, dof=dof, bytes=bytes_per_launch, kern_steady=kern_steady,
                          value=dof * 3 * args.steps / wall, ms_per_step=wall / args.steps * 1e3)
         log(f"{form}: {wall / args.steps * 1e3:.3f} ms/step, kernel {kern * 1e6:.1f} us/launch, "
             f"{bytes_per_launch / kern / 1e9:.0f} GB/s algorithmic")
@@ -511,17 +586,22 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None if traffic is None else traffic["bytes_per_launch"],
                      "traffic_over_algorithmic": None if traffic is None else traffic["over_algorithmic"],
-                     "kernel": "k_stage<3,3,EulerPhys<3>,double>",
+                     "kernel": "k_stage_n3 (3-D Euler, N=3, FP64)",
                      "kernel_us": f64["kern"] * 1e6, "bytes_per_launch": f64["bytes"]},
         "fp32": {"value": res["f32"]["value"], "kernel_us": res["f32"]["kern"] * 1e6,
                  "speedup_vs_fp64": f64["kern"] / res["f32"]["kern"],
                  "roofline_frac": res["f32"]["bytes"] / res["f32"]["kern"] / 1e9 / HBM_PEAK_GBS},
+        "steady_state": steady_summary(res, "after >= 0.2 s more of back-to-back steps (the clock the device "
+                                            "sustains under this load); the headline is the measurement above"),
     }
     if not args.no_extras:
+        log("64^3 workload ...")
+        out["euler3d_L"] = bench_large(args.steps, args.warmup)
         log("adjoint workload ...")
         out["adjoint"] = bench_adjoint(max(5, args.steps // 10))
         log("Navier-Stokes workload ...")
         out["navier_stokes"] = bench_navier_stokes(max(5, args.steps // 10))
+        out["navier_stokes_L"] = bench_navier_stokes(max(5, args.steps // 10), nel=(32, 32, 32))
         log("reacting workload ...")
         out["reacting"] = bench_reacting(max(5, args.steps // 10))
         log("two-temperature reacting workload ...")

@@ -45,13 +45,26 @@ PRESETS = {
 }
 
 
+def _torch_input(a):
+    return type(a).__module__.startswith("torch")
+
+
 def fourier_field(coords, lo, hi, seed, nmodes=4, kmax=2):
     """Smooth periodic field: sum of `nmodes` sines with integer wavevectors in
     {-kmax..kmax}^d minus 0, phases U[0, 2pi), amplitudes U[-1, 1], normalised
-    to max |f| = 1 over the given nodes.  coords: (dim, ...)."""
+    to max |f| = 1 over the given nodes.  coords: (dim, ...), a numpy array
+    or a torch tensor (then evaluated where it lives, e.g. on the device for
+    the large meshes; the random parameters are drawn on the host either
+    way)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     dim = coords.shape[0]
-    f = np.zeros(coords.shape[1:])
+    if _torch_input(coords):
+        import torch
+        f = torch.zeros(coords.shape[1:], dtype=coords.dtype, device=coords.device)
+        sin, amax = torch.sin, lambda x: float(x.abs().max())
+    else:
+        f = np.zeros(coords.shape[1:])
+        sin, amax = np.sin, lambda x: np.max(np.abs(x))
     for _ in range(nmodes):
         while True:
             k = rng.integers(-kmax, kmax + 1, size=dim)
@@ -59,14 +72,17 @@ def fourier_field(coords, lo, hi, seed, nmodes=4, kmax=2):
                 break
         phi = rng.uniform(0.0, TWO_PI)
         c = rng.uniform(-1.0, 1.0)
-        arg = phi + sum(TWO_PI * k[d] * (coords[d] - lo[d]) / (hi[d] - lo[d]) for d in range(dim))
-        f += c * np.sin(arg)
-    return f / np.max(np.abs(f))
+        arg = phi + sum(TWO_PI * int(k[d]) * (coords[d] - lo[d]) / (hi[d] - lo[d]) for d in range(dim))
+        f += c * sin(arg)
+    return f / amax(f)
 
 
 def conserved_from_primitive(rho, vel, p, gamma):
     """(rho, rho u, .., E) with E = p/(gamma-1) + rho |u|^2 / 2 (ideal gas)."""
     ke = 0.5 * rho * sum(v * v for v in vel)
+    if _torch_input(rho):
+        import torch
+        return torch.stack([rho] + [rho * v for v in vel] + [p / (gamma - 1.0) + ke])
     return np.stack([rho] + [rho * v for v in vel] + [p / (gamma - 1.0) + ke])
 
 
@@ -106,7 +122,7 @@ def random_euler(coords, lo, hi, gamma=1.4, mach=0.3, drho=0.05):
     dim = coords.shape[0]
     rho = 1.0 + drho * fourier_field(coords, lo, hi, seed=0)
     vel = [mach * fourier_field(coords, lo, hi, seed=1 + d) for d in range(dim)]
-    p = np.full_like(rho, 1.0 / gamma)
+    p = 0.0 * rho + 1.0 / gamma
     return conserved_from_primitive(rho, vel, p, gamma)
 
 

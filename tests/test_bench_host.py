@@ -25,7 +25,7 @@ def test_split_flop_count_per_element():
 
 
 def test_traffic_follows_the_committed_counters():
-    path = os.path.join(ROOT, "profiles", "k_stage_euler3d_f64_counters.json")
+    path = os.path.join(ROOT, "profiles", "k_stage_n3_euler3d_f64_counters.json")
     with open(path) as fh:
         c = json.load(fh)
     alg = bench.WORDS_PER_DOF_STAGE * 8 * 32 ** 3 * 64 * 5
