@@ -35,10 +35,10 @@ PRESETS = {
                   steps=200, batch=1),
     "air5_2d": dict(dim=2, N=3, nel=(64, 64), lo=(-1.0, -1.0), hi=(1.0, 1.0),
                     patch_lo=(24, 24), patch_hi=(40, 40), physics="reacting",
-                    cfl=0.5, steps=50, batch=1, mech_seed=42),
+                    cfl=0.5, steps=50, batch=1, mech_seed=42, mech_backward=(14.0, 22.0), rho0=0.1),
     "air5_2t_2d": dict(dim=2, N=3, nel=(64, 64), lo=(-1.0, -1.0), hi=(1.0, 1.0),
                        patch_lo=(24, 24), patch_hi=(40, 40), physics="reacting_2t",
-                       cfl=0.5, steps=50, batch=1, mech_seed=42),
+                       cfl=0.5, steps=50, batch=1, mech_seed=42, mech_backward=(12.0, 15.0), rho0=1.0e-3),
     "adjoint3d": dict(dim=3, N=3, nel=(16, 16, 16), lo=(0.0, 0.0, 0.0),
                       hi=(TWO_PI, TWO_PI, TWO_PI), physics="euler", gamma=1.4,
                       cfl=0.5, steps=50, batch=8),
@@ -173,7 +173,12 @@ W_O = 15.9994e-3
 SPECIES = ("N2", "O2", "NO", "N", "O")
 
 
-def air5_mechanism(seed=42):
+def preset_mechanism(p):
+    """The seeded mechanism of a reacting preset."""
+    return air5_mechanism(p["mech_seed"], backward=p["mech_backward"])
+
+
+def air5_mechanism(seed=42, backward=(14.0, 22.0)):
     """Seeded 5-species / 5-reaction air mechanism.
 
     Stoichiometry (reactants -> products over N2, O2, NO, N, O):
@@ -184,9 +189,11 @@ def air5_mechanism(seed=42):
     3/2 R_s (atoms); formation enthalpies per unit mass at 298 K from standard
     thermochemical tables (N2, O2 zero).  Rate constants are drawn, not
     physical: A log-uniform in [1e14, 1e22] (CGS), beta U[-1.5, 0], Theta
-    U[5e4, 1.2e5] K forward; backward triple A log-uniform in [1e12, 1e15]
-    (at or below the gas-kinetic collision limit), beta U[-1.5, 0], Theta
-    U[0, 2e4] K.  Third-body efficiencies all 1.
+    U[5e4, 1.2e5] K forward; backward triple A log-uniform in
+    [10^backward[0], 10^backward[1]] (default the forward range [1e14, 1e22];
+    the two-temperature workload takes [1e12, 1e15]), beta U[-1.5, 0], Theta
+    U[0, 2e4] K (the same random draws for every range).  Third-body
+    efficiencies all 1.
     Units: concentrations in mol/cm^3 (kappa_c = 1e-6 from mol/m^3), rates
     converted back to mol/(m^3 s) (kappa_r = 1e6).
     """
@@ -208,7 +215,7 @@ def air5_mechanism(seed=42):
     A_f = 10.0 ** rng.uniform(14.0, 22.0, size=5)
     beta_f = rng.uniform(-1.5, 0.0, size=5)
     theta_f = rng.uniform(5.0e4, 1.2e5, size=5)
-    A_b = 10.0 ** rng.uniform(12.0, 15.0, size=5)
+    A_b = 10.0 ** rng.uniform(backward[0], backward[1], size=5)
     beta_b = rng.uniform(-1.5, 0.0, size=5)
     theta_b = rng.uniform(0.0, 2.0e4, size=5)
     return dict(ns=5, nr=5, W=W, R=R, cv=cv, h0=h0, nu_f=nu_f, nu_b=nu_b,
@@ -219,7 +226,7 @@ def air5_mechanism(seed=42):
                 kappa_c=1.0e-6, kappa_r=1.0e6)
 
 
-def reacting_state(coords, lo, hi, mech, rho0=1.0e-3, T0=5000.0, dT=4000.0):
+def reacting_state(coords, lo, hi, mech, rho0=0.1, T0=5000.0, dT=4000.0):
     """Quiescent reacting state: T = T0 + dT g_T, rho = rho0 (1 + 0.05 g_rho),
     Y_s proportional to 0.05 + |g_s| normalised to sum 1, u = 0 (seeds 10, 11,
     12..16).  Conserved: (rho_s, 0, .., E) with E = sum rho_s (cv_s T + h0_s)."""

@@ -17,9 +17,21 @@ Implicit substep (eq. source_residual): Newton on
 T recovered from the closure at every evaluation.  Jacobian column k by a
 one-sided difference with eps_k = max(1e-7 |Y_k|, 1e-12) (the paper's rule);
 linear update by Gauss-Jordan elimination.  Readings where the paper is silent:
-start at Y* = Y^n; partial pivoting; after each update clip rho_s >= 0 (and
-count the clips); stop when max_k |dY_k| <= tol rho, or after max_iter
-iterations (then flag non-convergence).
+start at Y* = Y^n; partial pivoting; the step is halved while the clipped
+update would move T outside [T/2, 2T]; after each update clip rho_s >= 0 (and
+count the clips); converged when a full (undamped) step has max_k |dY_k| <=
+tol rho.
+
+Globalisation (reading): where h |dS/dY| is very large (dense gas, fast
+backward rates) Newton from Y^n can be drawn to a spurious corner -- a species
+driven to zero with a residual of order h |S| -- instead of the root.  A node
+not converged after max_iter iterations restarts from Y^n and follows the
+root along the substep length: the same Newton iteration solves the residual
+with h_j = h 2^-j for j = levels, .., 1, 0, each level starting from the
+previous level's result.  For small h_j the root is next to Y^n, and halving
+factors keep every level's start within reach of its root; the last level is
+the residual of the requested h.  Non-convergence is flagged only if that last
+level does not converge.
 """
 
 import math
@@ -127,31 +139,20 @@ def gauss_jordan(A, b):
     return b
 
 
-def implicit_substep(mech, dim, U, h, max_iter=25, tol=1e-13, max_halvings=30):
-    """One backward-Euler substep of length h on the species densities.
-
-    Returns (U_new, stats) with stats = dict(iters, unconverged, clips).
-    Momentum and total energy are copied unchanged.
-    """
-    ns = mech["ns"]
-    shape = U.shape
-    # flatten nodes: (ns, P)
-    rhos, m, E = split_state(mech, dim, U)
-    Yn = torch.stack([r.reshape(-1) for r in rhos])
-    mflat = [mm.reshape(-1) for mm in m]
-    Ef = E.reshape(-1)
-    rho = Yn.sum(dim=0)
-    ke = 0.5 * sum(mm * mm for mm in mflat) / rho
-    Y = Yn.clone()
+def _newton(mech, Y, Yn, h, ke, E, rho, max_iter, tol, max_halvings, stats):
+    """The Newton iteration on the residual of step length h for the nodes
+    (columns) of Y, from Y; returns (Y, converged mask, iterations)."""
+    ns = Y.shape[0]
+    Y = Y.clone()
     P = Y.shape[1]
     active = torch.ones(P, dtype=torch.bool)
+    conv = torch.zeros(P, dtype=torch.bool)
     iters = torch.zeros(P, dtype=torch.int64)
-    clips = 0
     for it in range(max_iter):
         if not bool(active.any()):
             break
         idx = active.nonzero().squeeze(1)
-        Ya, Yna, kea, Ea = Y[:, idx], Yn[:, idx], ke[idx], Ef[idx]
+        Ya, Yna, kea, Ea = Y[:, idx], Yn[:, idx], ke[idx], E[idx]
         R0, T0 = _residual(mech, Ya, Yna, h, kea, Ea)
         if bool((T0 <= 0).any()):
             raise NonPhysical("T <= 0 inside the implicit substep")
@@ -173,17 +174,49 @@ def implicit_substep(mech, dim, U, h, max_iter=25, tol=1e-13, max_halvings=30):
             if not bool(bad.any()):
                 break
             alpha = torch.where(bad, 0.5 * alpha, alpha)
+        full = alpha == 1.0
         dY = alpha * dY
         Ynew = Ya + dY
         neg = Ynew < 0
-        clips += int(neg.sum())
+        stats["clips"] += int(neg.sum())
         Ynew = torch.where(neg, torch.zeros_like(Ynew), Ynew)
         Y[:, idx] = Ynew
         iters[idx] += 1
-        done = dY.abs().max(dim=0).values <= tol * rho[idx]
+        done = full & (dY.abs().max(dim=0).values <= tol * rho[idx])
         active[idx[done]] = False
-    unconverged = int(active.sum())
+        conv[idx[done]] = True
+    return Y, conv, iters
+
+
+def implicit_substep(mech, dim, U, h, max_iter=25, tol=1e-13, max_halvings=30, levels=40):
+    """One backward-Euler substep of length h on the species densities.
+
+    Returns (U_new, stats) with stats = dict(iters, unconverged, clips,
+    continued): iters counts every Newton iteration of a node (all levels),
+    continued the nodes that took the continuation in h.  Momentum and total
+    energy are copied unchanged.
+    """
+    ns = mech["ns"]
+    shape = U.shape
+    # flatten nodes: (ns, P)
+    rhos, m, E = split_state(mech, dim, U)
+    Yn = torch.stack([r.reshape(-1) for r in rhos])
+    mflat = [mm.reshape(-1) for mm in m]
+    Ef = E.reshape(-1)
+    rho = Yn.sum(dim=0)
+    ke = 0.5 * sum(mm * mm for mm in mflat) / rho
+    stats = {"clips": 0}
+    Y, conv, iters = _newton(mech, Yn, Yn, h, ke, Ef, rho, max_iter, tol, max_halvings, stats)
+    cont = (~conv).nonzero().squeeze(1)
+    if len(cont) > 0:
+        Yc, Ync, kec, Ec, rhoc = Yn[:, cont].clone(), Yn[:, cont], ke[cont], Ef[cont], rho[cont]
+        cc = torch.zeros(len(cont), dtype=torch.bool)
+        for j in range(levels, -1, -1):
+            Yc, cc, ic = _newton(mech, Yc, Ync, h * 2.0 ** (-j), kec, Ec, rhoc, max_iter, tol, max_halvings, stats)
+            iters[cont] += ic
+        Y[:, cont] = Yc
+        conv[cont] = cc
     out = U.clone()
     for s in range(ns):
         out[:, s] = Y[s].reshape(shape[0], *shape[2:])
-    return out, dict(iters=iters, unconverged=unconverged, clips=clips)
+    return out, dict(iters=iters, unconverged=int((~conv).sum()), clips=stats["clips"], continued=len(cont))

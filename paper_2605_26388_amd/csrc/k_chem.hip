@@ -13,15 +13,24 @@
 //   eps_k = max(1e-7 |Y_k|, 1e-12); Gauss-Jordan elimination with partial
 //   pivoting in registers; the step is halved while the clipped update would
 //   move T outside [T/2, 2T] (temperature trust region, at most 30 halvings);
-//   species are clipped at 0 after the update (counted); stop when
-//   max |dY| <= tol rho or after max_iter iterations (then counted as
-//   unconverged).  The state of a node never leaves registers between
-//   evaluations; global traffic is one read and one write of the state.
+//   species are clipped at 0 after the update (counted); converged when a
+//   full (undamped) step has max |dY| <= tol rho.  A node not converged after
+//   max_iter iterations restarts from Y^n and follows the root along the
+//   substep length: the same iteration on the residual of h 2^-j for
+//   j = CONT_LEVELS, .., 1, 0, each level from the previous level's result
+//   (where h |dS/dY| is huge, Newton from Y^n can otherwise be drawn to a
+//   spurious corner with a species at zero); it counts as unconverged only if
+//   the last level does not converge.  The state of a node never leaves
+//   registers between evaluations; global traffic is one read and one write
+//   of the state.
 #include <algorithm>
 
 #include "dg_device.hpp"
 
 namespace dg {
+
+// levels of the continuation in the substep length (h 2^-40 .. h)
+constexpr int CONT_LEVELS = 40;
 
 template <int NS, int NR>
 struct Chem {
@@ -173,58 +182,67 @@ k_source(const T* U, T* out, const dg_mechanism* mech, size_t plane, int B, doub
     double Y[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) Y[s] = Yn[s];
-    bool converged = false;
     int it = 0, clips = 0;
-    for (; it < max_iter; ++it) {
-      double R0[NS];
-      const double T0 = chem.residual(Y, Yn, h, ke, E, R0);
-      if (!(T0 > 0.0)) {
-        report_nonphysical(counters, first_bad, t);
-        break;
-      }
-      double J[NS][NS];
-#pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        const double eps = fmax(1e-7 * fabs(Y[k]), 1e-12);
-        double Yp[NS], Rk[NS];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) Yp[s] = Y[s];
-        Yp[k] = Yp[k] + eps;
-        chem.residual(Yp, Yn, h, ke, E, Rk);
-#pragma unroll
-        for (int s = 0; s < NS; ++s) J[s][k] = (Rk[s] - R0[s]) / eps;
-      }
-      double rhs[NS], dY[NS];
-#pragma unroll
-      for (int s = 0; s < NS; ++s) rhs[s] = -R0[s];
-      gauss_jordan<NS>(J, rhs, dY);
-      double alpha = 1.0;
-      for (int hv = 0; hv < 30; ++hv) {
-        double Yt[NS];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) Yt[s] = fmax(Y[s] + alpha * dY[s], 0.0);
-        const double Tt = chem.temperature(Yt, ke, E);
-        if (!(Tt < 0.5 * T0) && !(Tt > 2.0 * T0)) break;
-        alpha *= 0.5;
-      }
-      double dmax = 0.0;
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        dY[s] = alpha * dY[s];
-        double y = Y[s] + dY[s];
-        if (y < 0.0) {
-          ++clips;
-          y = 0.0;
+    bool nonphys = false;
+    // Newton on the residual of step length hh from the current Y; returns
+    // whether a full step met the tolerance within max_iter iterations
+    auto newton = [&](double hh) -> bool {
+      for (int k_it = 0; k_it < max_iter; ++k_it) {
+        double R0[NS];
+        const double T0 = chem.residual(Y, Yn, hh, ke, E, R0);
+        if (!(T0 > 0.0)) {
+          nonphys = true;
+          return false;
         }
-        Y[s] = y;
-        dmax = fmax(dmax, fabs(dY[s]));
-      }
-      if (dmax <= tol * rho) {
-        converged = true;
         ++it;
-        break;
+        double J[NS][NS];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          const double eps = fmax(1e-7 * fabs(Y[k]), 1e-12);
+          double Yp[NS], Rk[NS];
+#pragma unroll
+          for (int s = 0; s < NS; ++s) Yp[s] = Y[s];
+          Yp[k] = Yp[k] + eps;
+          chem.residual(Yp, Yn, hh, ke, E, Rk);
+#pragma unroll
+          for (int s = 0; s < NS; ++s) J[s][k] = (Rk[s] - R0[s]) / eps;
+        }
+        double rhs[NS], dY[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) rhs[s] = -R0[s];
+        gauss_jordan<NS>(J, rhs, dY);
+        double alpha = 1.0;
+        for (int hv = 0; hv < 30; ++hv) {
+          double Yt[NS];
+#pragma unroll
+          for (int s = 0; s < NS; ++s) Yt[s] = fmax(Y[s] + alpha * dY[s], 0.0);
+          const double Tt = chem.temperature(Yt, ke, E);
+          if (!(Tt < 0.5 * T0) && !(Tt > 2.0 * T0)) break;
+          alpha *= 0.5;
+        }
+        double dmax = 0.0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          dY[s] = alpha * dY[s];
+          double y = Y[s] + dY[s];
+          if (y < 0.0) {
+            ++clips;
+            y = 0.0;
+          }
+          Y[s] = y;
+          dmax = fmax(dmax, fabs(dY[s]));
+        }
+        if (alpha == 1.0 && dmax <= tol * rho) return true;
       }
+      return false;
+    };
+    bool converged = newton(h);
+    if (!converged && !nonphys) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) Y[s] = Yn[s];
+      for (int j = CONT_LEVELS; j >= 0 && !nonphys; --j) converged = newton(ldexp(h, -j));
     }
+    if (nonphys) report_nonphysical(counters, first_bad, t);
     if (!converged) atomicAdd(&counters[CNT_NEWTON], 1);
     if (clips) atomicAdd(&counters[CNT_CLIPS], clips);
     atomicMax(&counters[CNT_ITERS], it);

@@ -28,7 +28,7 @@ def desc(dim=3, degree=3, nel=(4, 4, 4), physics=_abi.DG_EULER, precision=_abi.D
     if mech == "air5":
         import dginputs as di
         from paper_2605_26388_amd.solver import mechanism_struct
-        d._mech_keep = mechanism_struct(di.air5_mechanism(di.PRESETS["air5_2d"]["mech_seed"]))
+        d._mech_keep = mechanism_struct(di.preset_mechanism(di.PRESETS["air5_2d"]))
         mech = ctypes.pointer(d._mech_keep)
     d.mech = mech
     d.newton_max_iter, d.newton_tol, d.device = 25, 1e-13, 0
@@ -42,7 +42,7 @@ def desc(dim=3, degree=3, nel=(4, 4, 4), physics=_abi.DG_EULER, precision=_abi.D
     if vib == "air5":
         import dginputs as di
         from paper_2605_26388_amd.solver import vibration_struct
-        d._vib_keep = vibration_struct(di.air5_vibration(di.air5_mechanism(42)))
+        d._vib_keep = vibration_struct(di.air5_vibration(di.preset_mechanism(di.PRESETS["air5_2t_2d"])))
         d.vib = ctypes.pointer(d._vib_keep)
     return d
 

@@ -76,7 +76,7 @@ def test_fp32_rhs_navier_stokes():
 
 def test_fp32_rhs_reacting():
     P = di.PRESETS["air5_2d"]
-    mech = di.air5_mechanism(P["mech_seed"])
+    mech = di.preset_mechanism(P)
     op, s = make_pair(2, 3, (16, 16), P["lo"], P["hi"], physics="reacting", precision="f32",
                       patch=((6, 6), (10, 10)), mech=mech)
     U = torch.tensor(di.reacting_state(op.mesh.coords(), P["lo"], P["hi"], mech))[None]

@@ -19,7 +19,7 @@ P = di.PRESETS["air5_2d"]
 
 
 def workload(nel=None, patch=None, moving=True):
-    mech = di.air5_mechanism(P["mech_seed"])
+    mech = di.preset_mechanism(P)
     nel = nel or P["nel"]
     patch = patch or (P["patch_lo"], P["patch_hi"])
     op, s = make_pair(2, 3, nel, P["lo"], P["hi"], physics="reacting", patch=patch, mech=mech)
@@ -96,12 +96,18 @@ def test_implicit_substep_parity_full_workload():
     assert float(((got[:, :5] - ref[:, :5]).abs() / rho).max()) < 1e-11
     # momentum and energy are copied bit for bit
     assert torch.equal(out[:, 5:], Ug[:, 5:])
-    assert st["newton_iters_max"] <= 25
+    # the nodes that needed the continuation in h ran up to 25 iterations on
+    # each of its 41 levels after the first 25
+    print(f"implicit substep: oracle continued {info['continued']} nodes, max iterations oracle "
+          f"{int(info['iters'].max())} library {st['newton_iters_max']}", flush=True)
+    assert info["continued"] > 0
+    assert st["newton_iters_max"] <= 25 * 42
 
 
 def test_strang_step_matches_oracle():
     """Two Strang steps S_{dt/2} T_dt S_{dt/2} on the full reacting workload
-    (quiescent initial state, dt at CFL 0.5, where Newton converges)."""
+    (quiescent initial state, dt at CFL 0.5; the implicit substeps converge
+    everywhere, a few per cent of the nodes through the continuation in h)."""
     mech, op, s, U = workload(moving=False)
     Ug = to_gpu(s, U)
     dt = s.dt_cfl(Ug, P["cfl"])

@@ -21,7 +21,7 @@ P = di.PRESETS["air5_2t_2d"]
 
 
 def workload(nel=None, patch=None, u0=250.0):
-    mech = di.air5_mechanism(P["mech_seed"])
+    mech = di.preset_mechanism(P)
     vib = di.air5_vibration(mech)
     nel = nel or P["nel"]
     patch = patch or (P["patch_lo"], P["patch_hi"])

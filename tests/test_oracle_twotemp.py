@@ -21,7 +21,7 @@ from oracle.twotemp import (ReactingEuler2T, e_vib, implicit_substep, q_vt, sour
                             wdot_2t)
 from oracle.timestep import integrals
 
-MECH = di.air5_mechanism(di.PRESETS["air5_2t_2d"]["mech_seed"])
+MECH = di.preset_mechanism(di.PRESETS["air5_2t_2d"])
 VIB = di.air5_vibration(MECH)
 ATOMS = np.array([[2, 0], [0, 2], [1, 1], [1, 0], [0, 1]])    # (N, O) atoms per species
 
