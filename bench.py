@@ -119,9 +119,12 @@ def time_stages(solver, U, dt, steps, warmup, steady=False):
     return wall, kern, kern_steady
 
 
-def time_adjoint(solver, U, dt, steps, warmup):
+def time_adjoint(solver, U, dt, steps, warmup, recompute=False):
     """Adjoint of SSP-RK3 steps with stored stage states: per step three
-    dg_rk_stage_adjoint launches.  Returns (wall s per step, mean launch s)."""
+    dg_rk_stage_adjoint launches; with recompute=True (step checkpoints) the
+    two forward stages of the step are recomputed from U^n first, as the
+    rollout's "steps" checkpointing does.  Returns (wall s per step, mean
+    launch s)."""
     Us = [U.clone(), solver.empty(), solver.empty()]
     solver.rk_stage(None, Us[0], Us[1], 0.0, 1.0, dt)
     solver.rk_stage(Us[0], Us[1], Us[2], 0.75, 0.25, 0.25 * dt)
@@ -129,6 +132,9 @@ def time_adjoint(solver, U, dt, steps, warmup):
     mu2, mu1, acc, out = solver.empty(), solver.empty(), solver.empty(), solver.empty()
 
     def step():
+        if recompute:
+            solver.rk_stage(None, Us[0], Us[1], 0.0, 1.0, dt)
+            solver.rk_stage(Us[0], Us[1], Us[2], 0.75, 0.25, 0.25 * dt)
         solver.ssprk3_step_adjoint(Us, dt, lam, out, acc, mu2, mu1)
 
     for _ in range(warmup):
@@ -332,6 +338,9 @@ def bench_reacting(reps):
     src1 = time_calls(lambda: s.source_chem(U0, out1, 0.5 * dt, 1), reps)
     st = s.status()
     strang = time_calls(lambda: s.strang_step(U, dt, t1, t2), max(2, reps // 4), reset=restore)
+    t3 = s.empty()
+    strang54 = time_calls(lambda: s.strang_step(U, 1.508 * dt, t1, t2, t3, transport="ssprk54"), max(2, reps // 4),
+                          reset=restore)
     st2 = s.status()
     s.close()
     return {"workload": "air5_2d: reacting Euler 64^2 + 2:1 16^2 patch, N=3, 5-species air, rho about 0.1 kg/m^3, "
@@ -339,7 +348,9 @@ def bench_reacting(reps):
             "stage_ms": stage * 1e3, "source_mode0_node_evals_per_s": nodes / src0,
             "source_mode1_nodes_per_s": nodes / src1, "source_mode1_ms": src1 * 1e3,
             "newton_iters_max": st["newton_iters_max"], "newton_unconverged": st["newton_unconverged"],
-            "strang_step_ms": strang * 1e3, "strang_nonphysical": st2["nonphysical"],
+            "strang_step_ms": strang * 1e3,
+            "strang_ssprk54_step_ms": strang54 * 1e3, "strang_ssprk54_dt_over_ssprk3": 1.508,
+            "strang_nonphysical": st2["nonphysical"],
             "strang_newton_unconverged": st2["newton_unconverged"]}
 
 
@@ -491,8 +502,11 @@ def bench_adjoint(steps):
         U0 = U.clone()
         fwd = time_calls(lambda: s.ssprk3_step(U, dt, t1, t2), steps, reset=lambda: U.copy_(U0))
         bwd_step, _ = time_adjoint(s, U, dt, steps, 2)
+        bwd_rec, _ = time_adjoint(s, U, dt, steps, 2, recompute=True)
         out[prec] = {"forward_ms_per_step": fwd * 1e3, "backward_ms_per_step": bwd_step * 1e3,
-                     "backward_over_forward": bwd_step / fwd}
+                     "backward_over_forward": bwd_step / fwd,
+                     "backward_recompute_ms_per_step": bwd_rec * 1e3,
+                     "backward_recompute_over_forward": bwd_rec / fwd}
         s.close()
     out["workload"] = "adjoint3d: 3-D Euler 16^3, N=3, batch 8 (10,485,760 DOF), stored stage states"
     return out

@@ -239,10 +239,17 @@ class Solver:
         self.rk_stage(U, t2, U, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0 * dt)
         return U
 
-    def strang_step(self, U, dt, tmp1=None, tmp2=None):
+    def strang_step(self, U, dt, tmp1=None, tmp2=None, tmp3=None, transport="ssprk3"):
         """S_{dt/2} o T_dt o S_{dt/2}: implicit source half steps around one
-        SSP-RK3 transport step (eq. strang_split), in place on U."""
+        transport step (eq. strang_split), in place on U.  transport is
+        "ssprk3" (three Shu-Osher stages; scratch tmp1, tmp2) or "ssprk54"
+        (the paper's five-stage method; scratch tmp1, tmp2, tmp3)."""
         self.source_chem(U, U, 0.5 * dt, 1)
-        self.ssprk3_step(U, dt, tmp1, tmp2)
+        if transport == "ssprk54":
+            self.ssprk54_step(U, dt, tmp1, tmp2, tmp3)
+        elif transport == "ssprk3":
+            self.ssprk3_step(U, dt, tmp1, tmp2)
+        else:
+            raise ValueError(f"unknown transport step {transport!r}")
         self.source_chem(U, U, 0.5 * dt, 1)
         return U

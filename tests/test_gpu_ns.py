@@ -4,6 +4,7 @@ workload (16^3, N = 4), conservation, and the TGV viscous-dissipation identity
 evaluated from the library's own right-hand sides."""
 
 import math
+import os
 
 import numpy as np
 import pytest
@@ -79,3 +80,45 @@ def test_tgv_viscous_dissipation_on_gpu():
     val = eu.integrals(tmp)[0, 0] / TWO_PI ** 3
     assert abs(val / (-0.75 * P["mu"]) - 1.0) < 1e-2
     assert float(dv[:, 0].abs().max()) < 1e-12
+
+
+@pytest.mark.skipif(os.environ.get("DG_LONG", "0") != "1",
+                    reason="full-length run (minutes of CPU oracle time): set DG_LONG=1")
+def test_full_length_tgv_200_steps():
+    """The Taylor-Green workload at its full size and length: 16^3, N = 4,
+    200 SSP-RK3 steps, the library in FP64 and in the FP32 form against the
+    oracle's FP64 run.  FP64: each of the 600 stages adds at most dt times
+    the right-hand side's bound (16 oracle rounding spreads, about 1e-11 of
+    the flux scale) plus a few units in the last place of U: 1e-10 of each
+    variable's norm covers the run.  FP32: the stated 1e-4.  The momentum is
+    measured as one vector (its z component starts at zero).  The workload
+    states no CFL; it runs at 0.25 (at 0.5 the 3-D N = 4 operator is not
+    stable under SSP-RK3)."""
+    from oracle.timestep import ssprk33_step
+    op, s64 = make_pair(3, P["N"], P["nel"], P["lo"], P["hi"], physics="navier_stokes",
+                        mu=P["mu"], prandtl=P["prandtl"])
+    _, s32 = make_pair(3, P["N"], P["nel"], P["lo"], P["hi"], physics="navier_stokes", precision="f32",
+                       mu=P["mu"], prandtl=P["prandtl"])
+    U = torch.tensor(di.taylor_green(op.mesh.coords(), mach=P["mach"]))[None]
+    g64, g32 = to_gpu(s64, U), to_gpu(s32, U)
+    dt = s64.dt_cfl(g64, P["cfl"])
+
+    def err(got, ref):
+        # norm-wise per variable; the momentum is one vector, its components
+        # measured against the largest component's norm (m_z starts at zero)
+        d = (got - ref).reshape(5, -1).abs().amax(dim=1)
+        n = ref.reshape(5, -1).abs().amax(dim=1)
+        n[1:4] = n[1:4].max()
+        return float((d / n).max())
+
+    for k in range(200):
+        U = ssprk33_step(op, U, dt)
+        s64.ssprk3_step(g64, dt)
+        s32.ssprk3_step(g32, dt)
+        if k % 50 == 49:
+            print(f"step {k + 1}: FP64 {err(from_gpu(op, g64), U):.3e}, FP32 {err(from_gpu(op, g32), U):.3e} "
+                  f"(per component: FP32 {rel_err(from_gpu(op, g32), U):.3e})", flush=True)
+    e64, e32 = err(from_gpu(op, g64), U), err(from_gpu(op, g32), U)
+    print(f"TGV 16^3 N=4 after 200 steps: FP64 {e64:.3e}, FP32 {e32:.3e}", flush=True)
+    assert e64 < 1e-10
+    assert e32 < 1e-4

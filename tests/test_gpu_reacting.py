@@ -4,6 +4,7 @@
 reacting workload (64^2 + refined 16^2 block, N=3, 5-species air)."""
 
 import math
+import os
 
 import numpy as np
 import pytest
@@ -11,6 +12,7 @@ import torch
 
 import dginputs as di
 from oracle import chem
+from oracle.ssprk54 import ssprk54_step
 from oracle.timestep import rk_stage, ssprk33_step, dt_cfl
 from helpers import make_pair, to_gpu, from_gpu, rel_err
 
@@ -117,6 +119,62 @@ def test_strang_step_matches_oracle():
         U, i2 = chem.implicit_substep(mech, 2, U, 0.5 * dt)
         assert i1["unconverged"] == 0 and i2["unconverged"] == 0
         s.strang_step(Ug, dt)
+    got = from_gpu(op, Ug)
+    rho = U[:, :5].sum(1, keepdim=True)
+    assert float(((got[:, :5] - U[:, :5]).abs() / rho).max()) < 1e-10
+    assert rel_err(got[:, 5:], U[:, 5:]) < 1e-10
+    st = s.status()
+    assert st["newton_unconverged"] == 0 and st["nonphysical"] == 0
+
+
+def test_strang_step_with_ssprk54_matches_oracle():
+    """The paper's Strang step: the transport step T_dt taken with SSPRK54
+    (at its larger SSP step, 1.508 x the SSP-RK3 CFL step), two steps on the
+    full reacting workload against the oracle's SSPRK54 on the reacting
+    operator, with the mortar patch and a moving state."""
+    mech, op, s, U = workload()
+    Ug = to_gpu(s, U)
+    dt = 1.508 * s.dt_cfl(Ug, P["cfl"])
+    t1, t2, t3 = s.empty(), s.empty(), s.empty()
+    for _ in range(2):
+        U, i1 = chem.implicit_substep(mech, 2, U, 0.5 * dt)
+        U = ssprk54_step(op, U, dt)
+        U, i2 = chem.implicit_substep(mech, 2, U, 0.5 * dt)
+        assert i1["unconverged"] == 0 and i2["unconverged"] == 0
+        s.strang_step(Ug, dt, t1, t2, t3, transport="ssprk54")
+    got = from_gpu(op, Ug)
+    rho = U[:, :5].sum(1, keepdim=True)
+    err_y = float(((got[:, :5] - U[:, :5]).abs() / rho).max())
+    err_m = rel_err(got[:, 5:], U[:, 5:])
+    print(f"Strang with SSPRK54, two steps: species {err_y:.3e}, momentum/energy {err_m:.3e}", flush=True)
+    assert err_y < 1e-10
+    assert err_m < 1e-10
+    st = s.status()
+    assert st["newton_unconverged"] == 0 and st["nonphysical"] == 0
+
+
+@pytest.mark.skipif(os.environ.get("DG_LONG", "0") != "1",
+                    reason="full-length run (minutes of CPU oracle time): set DG_LONG=1")
+def test_full_length_50_strang_steps():
+    """The reacting workload at its full length: 50 Strang steps (SSP-RK3
+    transport at CFL 0.5, implicit source half steps) on the full mesh with a
+    moving state, against the oracle.  Every substep converges on both sides;
+    species to 1e-10 of the density, momentum and energy to 1e-10 norm-wise."""
+    mech, op, s, U = workload()
+    Ug = to_gpu(s, U)
+    dt = s.dt_cfl(Ug, P["cfl"])
+    t1, t2 = s.empty(), s.empty()
+    for k in range(50):
+        U, i1 = chem.implicit_substep(mech, 2, U, 0.5 * dt)
+        U = ssprk33_step(op, U, dt)
+        U, i2 = chem.implicit_substep(mech, 2, U, 0.5 * dt)
+        assert i1["unconverged"] == 0 and i2["unconverged"] == 0
+        s.strang_step(Ug, dt, t1, t2)
+        if k % 10 == 9:
+            got = from_gpu(op, Ug)
+            rho = U[:, :5].sum(1, keepdim=True)
+            print(f"Strang step {k + 1}: species {float(((got[:, :5] - U[:, :5]).abs() / rho).max()):.3e}, "
+                  f"momentum/energy {rel_err(got[:, 5:], U[:, 5:]):.3e}", flush=True)
     got = from_gpu(op, Ug)
     rho = U[:, :5].sum(1, keepdim=True)
     assert float(((got[:, :5] - U[:, :5]).abs() / rho).max()) < 1e-10
