@@ -613,23 +613,29 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
 
 // ---------------------------------------------------------------------------
 // The headline shape -- 3-D, N = 3 (64 nodes: one element per single-wave
-// workgroup), conforming faces, FP64 -- with every global read of the stage
-// issued at the start, so that a wave waits for memory once instead of three
-// times (own state, then neighbour face nodes, then U0):
+// workgroup), conforming faces, FP64 and the FP32 form -- with every global
+// read of the stage issued at the start, so that a wave waits for memory once
+// instead of three times (own state, then neighbour face nodes, then U0):
 //   * U_k of the element's own nodes into registers (coalesced);
 //   * the neighbour face nodes of all three directions straight into LDS by
 //     buffer-to-LDS loads (no registers held): per direction and variable
-//     one 4-byte load per lane, lane L fetching dword L & 1 of face slot
-//     L >> 1 (slots 0-15 the -xi_l face, 16-31 the +xi_l face, tangential
-//     index a + 4 b in the two other directions);
-//   * U0, when the stage reads it, into LDS by 16-byte loads (two variables
-//     per instruction).
+//     one 4-byte load per lane -- in FP64 lane L fetches dword L & 1 of face
+//     slot L >> 1, in FP32 lane L < 32 fetches slot L (slots 0-15 the -xi_l
+//     face, 16-31 the +xi_l face, tangential index a + 4 b in the two other
+//     directions);
+//   * U0, when the stage reads it: FP64 into registers right after those
+//     loads (96 VGPRs, 5 waves per SIMD, and the LDS stays at 6.8 KB so it
+//     does not limit the waves either -- measured faster than loading it into
+//     LDS), FP32 into LDS by one 4-byte load per variable.
 // The directions are then processed one after the other: the flux along l
 // is staged in LDS, swept with D (scaled by -2/h_l), and the lanes on an l
 // face apply their interface correction with the own flux still in
 // registers.  Being one wave, the workgroup needs no barrier: LDS accesses of
 // a wave complete in order, and a wave-level fence keeps the compiler from
-// reordering them.  Same arithmetic per term as k_stage.
+// reordering them.  Same arithmetic per term as k_stage, including the FP32
+// form's conventions (fluxes and face corrections in double, the staged
+// flux minus the element's first-node flux rounded to float, float sweep,
+// accumulator and stage combination).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -639,14 +645,26 @@ __device__ __forceinline__ void wave_lds_fence() {
 
 #define DG_LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
 
+// double value of lane 0 (wave-uniform)
+__device__ __forceinline__ double lane0(double x) {
+  const u32x2 w = __builtin_bit_cast(u32x2, x);
+  u32x2 r;
+  r.x = __builtin_amdgcn_readfirstlane(w.x);
+  r.y = __builtin_amdgcn_readfirstlane(w.y);
+  return __builtin_bit_cast(double, r);
+}
+
+template <typename T>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
 k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
   using PHYS = EulerPhys<3>;
   constexpr int DIM = 3, N = 3, n = 4, NP = 64, NV = 5;
-  __shared__ double sF[NV][NP];
-  __shared__ double sDg[DIM][n * n];
-  __shared__ __attribute__((aligned(16))) unsigned sNb[DIM][NV][64];  // [l][v][2 * slot + half]
-  __shared__ __attribute__((aligned(16))) double sU0[NV + 1][NP];  // spare row: see the U0 loads below
+  constexpr bool F32 = std::is_same<T, float>::value;
+  constexpr int WPV = F32 ? 32 : 64;  // dwords of face data per direction and variable
+  __shared__ T sF[NV][NP];
+  __shared__ T sDg[DIM][n * n];
+  __shared__ __attribute__((aligned(16))) unsigned sNb[DIM][NV][WPV];
+  __shared__ __attribute__((aligned(16))) T sU0[F32 ? NV : 1][F32 ? NP : 1];
 
   const int tid = threadIdx.x;
   const double dsc = tid < n * n ? mv.K->D[tid] : 0.0;
@@ -667,40 +685,46 @@ k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
   const int stride[3] = {1, 4, 16};
 
   const size_t plane = (size_t)E * NP;
-  const size_t abytes = (size_t)NV * plane * sizeof(double);
-  const unsigned pstride = (unsigned)(plane * sizeof(double));
-  const rsrc_t rU = make_rsrc(static_cast<const double*>(sp.Uk) + (size_t)b * NV * plane, abytes);
+  const size_t abytes = (size_t)NV * plane * sizeof(T);
+  const unsigned pstride = (unsigned)(plane * sizeof(T));
+  const rsrc_t rU = make_rsrc(static_cast<const T*>(sp.Uk) + (size_t)b * NV * plane, abytes);
   const unsigned off = (unsigned)(ec * NP + tid);
 
   // own state into registers
   double u[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) u[v] = Buf<double>::load(rU, off, v * pstride);
+  for (int v = 0; v < NV; ++v) u[v] = Buf<T>::load(rU, off, v * pstride);
   // neighbour face nodes into LDS
   {
-    const int slot = tid >> 1, half = tid & 1, side = slot >> 4, ta = slot & 3, tb = (slot >> 2) & 3;
+    const int slot = F32 ? tid : tid >> 1, half = F32 ? 0 : tid & 1;
+    const bool upper = (slot & 16) != 0;  // slot on the +xi_l face
+    const int ta = slot & 3, tb = (slot >> 2) & 3;
+    if (!F32 || tid < 32) {
 #pragma unroll
-    for (int l = 0; l < DIM; ++l) {
-      const int o1 = l == 0 ? 1 : 0, o2 = l == 2 ? 1 : 2;
-      const int ne = side ? nbl[2 * l + 1] : nbl[2 * l];
-      const int node = (side ? 0 : N) * stride[l] + ta * stride[o1] + tb * stride[o2];
-      const unsigned voff = (unsigned)(ne * NP + node) * 8u + 4u * (unsigned)half;
+      for (int l = 0; l < DIM; ++l) {
+        const int o1 = l == 0 ? 1 : 0, o2 = l == 2 ? 1 : 2;
+        const int lo = nbl[2 * l], hi = nbl[2 * l + 1];
+        const int ne = upper ? hi : lo;
+        const int node = (upper ? 0 : N) * stride[l] + ta * stride[o1] + tb * stride[o2];
+        const unsigned voff = (unsigned)(ne * NP + node) * (unsigned)sizeof(T) + 4u * (unsigned)half;
 #pragma unroll
-      for (int v = 0; v < NV; ++v)
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rU, DG_LDS_PTR(&sNb[l][v][0]), 4, voff, v * pstride, 0, 0);
+        for (int v = 0; v < NV; ++v)
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(rU, DG_LDS_PTR(&sNb[l][v][0]), 4, voff, v * pstride, 0, 0);
+      }
     }
   }
   const bool use_u0 = (sp.mode != 0) && (sp.a != 0.0);
-  if (use_u0) {
-    const rsrc_t r0 = make_rsrc(static_cast<const double*>(sp.U0) + (size_t)b * NV * plane, abytes);
+  double u0r[NV];  // FP64: U0 in registers
+  if (!F32 && use_u0) {
+    const rsrc_t r0 = make_rsrc(static_cast<const T*>(sp.U0) + (size_t)b * NV * plane, abytes);
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const int v = 2 * q + (tid >> 5);
-      if (v < NV) {
-        const unsigned voff = (unsigned)v * pstride + (unsigned)(ec * NP + 2 * (tid & 31)) * 8u;
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(r0, DG_LDS_PTR(&sU0[2 * q][0]), 16, voff, 0, 0, 0);
-      }
-    }
+    for (int v = 0; v < NV; ++v) u0r[v] = Buf<T>::load(r0, off, v * pstride);
+  }
+  if (F32 && use_u0) {  // FP32: U0 into LDS
+    const rsrc_t r0 = make_rsrc(static_cast<const T*>(sp.U0) + (size_t)b * NV * plane, abytes);
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(r0, DG_LDS_PTR(&sU0[v][0]), 4, off * 4u, v * pstride, 0, 0);
   }
 
   Thermo th;
@@ -709,25 +733,29 @@ k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
   double vel[DIM];
 #pragma unroll
   for (int d = 0; d < DIM; ++d) vel[d] = u[1 + d] * th.ri;
-  const double aown = wave_sound<PHYS, false>(th);
+  const double aown = wave_sound<PHYS, F32>(th);
   if (tid < n * n) {
 #pragma unroll
-    for (int l = 0; l < DIM; ++l) sDg[l][tid] = -g[l] * dsc;
+    for (int l = 0; l < DIM; ++l) sDg[l][tid] = static_cast<T>(-g[l] * dsc);
   }
 
-  double acc[NV];
+  T acc[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  for (int v = 0; v < NV; ++v) acc[v] = T(0);
 #pragma unroll
   for (int l = 0; l < DIM; ++l) {
     double F[NV];
     PHYS::flux(u, vel[l], th.p, l, F);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) sF[v][tid] = F[v];
+    for (int v = 0; v < NV; ++v) {
+      // FP32: relative to the element's first node (D annihilates constants)
+      if constexpr (F32) sF[v][tid] = static_cast<float>(F[v] - lane0(F[v]));
+      else sF[v][tid] = F[v];
+    }
     wave_lds_fence();
     // volume integral along l
     const int il = ii[l], st = stride[l], base = tid - il * st;
-    double drow[n];
+    T drow[n];
 #pragma unroll
     for (int m = 0; m < n; ++m) drow[m] = sDg[l][il * n + m];
 #pragma unroll
@@ -741,49 +769,67 @@ k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
       const int slot = side * 16 + ii[o1] + 4 * ii[o2];
       double un[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) un[v] = *reinterpret_cast<const double*>(&sNb[l][v][2 * slot]);
+      for (int v = 0; v < NV; ++v) {
+        if constexpr (F32) un[v] = static_cast<double>(__builtin_bit_cast(float, sNb[l][v][slot]));
+        else un[v] = *reinterpret_cast<const double*>(&sNb[l][v][2 * slot]);
+      }
       Thermo tn;
       PHYS::thermo(un, tn, pc);
       const double vn = un[1 + l] * tn.ri;
       double Fn[NV];
       PHYS::flux(un, vn, tn.p, l, Fn);
       const double co = fabs(vel[l]) + aown;
-      const double cn = fabs(vn) + wave_sound<PHYS, false>(tn);
+      const double cn = fabs(vn) + wave_sound<PHYS, F32>(tn);
       const double lam = fmax(co, cn);
       const double sgn = side == 1 ? 1.0 : -1.0;
       const double hs = sgn * lam;
       const double sc = -sgn * (g[l] * hwinv);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) acc[v] = fma(sc, fma(-hs, un[v] - u[v], Fn[v] - F[v]), acc[v]);
+      for (int v = 0; v < NV; ++v) {
+        const double dv = fma(-hs, un[v] - u[v], Fn[v] - F[v]);
+        if constexpr (F32) acc[v] = fma(static_cast<float>(sc), static_cast<float>(dv), acc[v]);
+        else acc[v] = fma(sc, dv, acc[v]);
+      }
     }
     wave_lds_fence();  // the next direction overwrites sF
   }
 
   // ---- output ----------------------------------------------------------------
-  const rsrc_t ro = make_rsrc(static_cast<double*>(sp.out) + (size_t)b * NV * plane, abytes);
+  const rsrc_t ro = make_rsrc(static_cast<T*>(sp.out) + (size_t)b * NV * plane, abytes);
   if (sp.mode == 0) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Buf<double>::store(ro, off, acc[v], v * pstride);
+    for (int v = 0; v < NV; ++v) Buf<T>::store(ro, off, acc[v], v * pstride);
     return;
   }
-  double r[NV];
+  T r[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    r[v] = fma(sp.c, acc[v], sp.b * u[v]);
-    if (use_u0) r[v] = fma(sp.a, sU0[v][tid], r[v]);
+    r[v] = fma(T(sp.c), acc[v], T(sp.b) * T(u[v]));
+    if (use_u0) r[v] = fma(T(sp.a), F32 ? sU0[v][tid] : T(u0r[v]), r[v]);
   }
-  if (sp.rho_min > 0.0 || sp.p_min > 0.0) positivity_floor(r, sp.rho_min, sp.p_min, 1.0 / (pc.gamma - 1.0), mv.counters);
+  if (sp.rho_min > 0.0 || sp.p_min > 0.0) {  // the floor itself in double
+    if constexpr (F32) {
+      double rd[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) Buf<double>::store(ro, off, r[v], v * pstride);
+      for (int v = 0; v < NV; ++v) rd[v] = r[v];
+      positivity_floor(rd, sp.rho_min, sp.p_min, 1.0 / (pc.gamma - 1.0), mv.counters);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) r[v] = T(rd[v]);
+    } else {
+      positivity_floor(r, sp.rho_min, sp.p_min, 1.0 / (pc.gamma - 1.0), mv.counters);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) Buf<T>::store(ro, off, r[v], v * pstride);
   if (sp.mode == 2) {  // second combination of the same L(Uk), no floor
-    const rsrc_t r2 = make_rsrc(static_cast<double*>(sp.out2) + (size_t)b * NV * plane, abytes);
+    const rsrc_t r2 = make_rsrc(static_cast<T*>(sp.out2) + (size_t)b * NV * plane, abytes);
     const bool use_v = sp.a2 != 0.0;
-    const rsrc_t rv = make_rsrc(static_cast<const double*>(use_v ? sp.V : sp.Uk) + (size_t)b * NV * plane, abytes);
+    const rsrc_t rv = make_rsrc(static_cast<const T*>(use_v ? sp.V : sp.Uk) + (size_t)b * NV * plane, abytes);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      double w = fma(sp.c2, acc[v], sp.b2 * u[v]);
-      if (use_v) w = fma(sp.a2, Buf<double>::load(rv, off, v * pstride), w);
-      Buf<double>::store(r2, off, w, v * pstride);
+      T w = fma(T(sp.c2), acc[v], T(sp.b2) * T(u[v]));
+      if (use_v) w = fma(T(sp.a2), T(Buf<T>::load(rv, off, v * pstride)), w);
+      Buf<T>::store(r2, off, w, v * pstride);
     }
   }
 }
@@ -860,9 +906,8 @@ static hipError_t go(const Ctx& c, const StageParams& sp, hipStream_t s) {
   using SH = Shape<DIM, N>;
   const int nEB = (c.E + SH::EPB - 1) / SH::EPB;
   const int nblk = nEB * c.B;
-  if constexpr (DIM == 3 && N == 3 && std::is_same<PHYS, EulerPhys<3>>::value && std::is_same<T, double>::value &&
-                !MORTAR && !SPLIT) {
-    hipLaunchKernelGGL(k_stage_n3, dim3(nblk), dim3(64), 0, s, sp, mesh_view(c), c.pc);
+  if constexpr (DIM == 3 && N == 3 && std::is_same<PHYS, EulerPhys<3>>::value && !MORTAR && !SPLIT) {
+    hipLaunchKernelGGL(k_stage_n3<T>, dim3(nblk), dim3(64), 0, s, sp, mesh_view(c), c.pc);
     return hipGetLastError();
   }
   hipLaunchKernelGGL((k_stage<DIM, N, PHYS, T, MORTAR, SPLIT>), dim3(nblk), dim3(SH::BS), 0, s, sp, mesh_view(c),
