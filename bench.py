@@ -297,14 +297,14 @@ def bench_large(steps, warmup):
     return res
 
 
-def bench_navier_stokes(reps, nel=None):
+def bench_navier_stokes(reps, nel=None, volume="standard"):
     from paper_2605_26388_amd import Solver
     p = di.PRESETS["tgv3d"]
     nel = tuple(nel) if nel else tuple(p["nel"])
     out = {}
     for prec in ("f64", "f32"):
         s = Solver(3, p["N"], nel, p["lo"], p["hi"], physics="navier_stokes", precision=prec,
-                   mu=p["mu"], prandtl=p["prandtl"])
+                   mu=p["mu"], prandtl=p["prandtl"], volume=volume)
         X = s.node_coords().cpu().numpy()
         U = torch.tensor(di.taylor_green(X, mach=p["mach"]))[None].to(s.device, s.dtype).contiguous()
         dt = s.dt_cfl(U, p["cfl"])
@@ -314,7 +314,8 @@ def bench_navier_stokes(reps, nel=None):
         dof = s.E * s.Np * s.nv
         out[prec] = {"ms_per_stage": step / 3 * 1e3, "dof_updates_per_s": 3 * dof / step}
         s.close()
-    out["workload"] = (f"tgv3d: Navier-Stokes TGV {nel[0]}^3, N=4, Re 1600, Mach 0.1, BR1 (two passes per stage)")
+    out["workload"] = (f"tgv3d: Navier-Stokes TGV {nel[0]}^3, N=4, Re 1600, Mach 0.1, BR1 (two passes per stage)"
+                       + (", split-form (Ranocha) inviscid volume integral" if volume == "split" else ""))
     return out
 
 
@@ -523,7 +524,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--only", choices=["f64", "f32"], default=None,
                     help="time one form only (profiling runs)")
-    ap.add_argument("--side", choices=["adjoint", "navier_stokes", "navier_stokes_L", "reacting", "reacting_2t", "split",
+    ap.add_argument("--side", choices=["adjoint", "navier_stokes", "navier_stokes_L", "navier_stokes_split", "reacting",
+                                       "reacting_2t", "split",
                                        "ssprk54", "curvilinear"],
                     default=None,
                     help="instead: run one side workload alone and print its JSON (profiling runs)")
@@ -550,6 +552,7 @@ def main():
         fn = {"adjoint": lambda: bench_adjoint(reps),
               "navier_stokes": lambda: bench_navier_stokes(reps),
               "navier_stokes_L": lambda: bench_navier_stokes(reps, nel=(32, 32, 32)),
+              "navier_stokes_split": lambda: bench_navier_stokes(reps, volume="split"),
               "reacting": lambda: bench_reacting(reps),
               "reacting_2t": lambda: bench_reacting_2t(reps),
               "split": lambda: bench_split(args.steps, args.warmup),
@@ -621,6 +624,7 @@ def main():
         log("Navier-Stokes workload ...")
         out["navier_stokes"] = bench_navier_stokes(max(5, args.steps // 10))
         out["navier_stokes_L"] = bench_navier_stokes(max(5, args.steps // 10), nel=(32, 32, 32))
+        out["navier_stokes_split"] = bench_navier_stokes(max(5, args.steps // 10), volume="split")
         log("reacting workload ...")
         out["reacting"] = bench_reacting(max(5, args.steps // 10))
         log("two-temperature reacting workload ...")

@@ -81,14 +81,16 @@ enum dg_physics { DG_EULER = 0, DG_NAVIER_STOKES = 1, DG_REACTING_EULER = 2, DG_
  *   keeps its sweep, accumulation and stage combination in double in both. */
 enum dg_precision { DG_F64 = 0, DG_F32 = 1 };
 
-/* Volume integral of the Euler operator.
+/* Volume integral of the inviscid flux.
  * DG_VOLUME_STANDARD: strong form of eq. vol_weak, sum_m D_im F_l(U_m).
  * DG_VOLUME_SPLIT: entropy-conservative split form (eq. vol_split, the
  *   appendix on the inviscid volume flux): 2 sum_m D_im F#_l(U_i, U_m) with
  *   Ranocha's kinetic-energy-preserving, entropy-conservative two-point flux
  *   in its published form (the energy row as printed in the paper is not
- *   entropy conservative), logarithmic means of rho and rho/p.  Euler
- *   physics only; the interface flux stays Rusanov; no adjoint. */
+ *   entropy conservative), logarithmic means of rho and rho/p.  Euler and
+ *   Navier-Stokes physics (with the BR1 viscous terms unchanged, the paper's
+ *   Taylor-Green setting) on Cartesian meshes; the interface flux stays
+ *   Rusanov; no adjoint. */
 enum dg_volume { DG_VOLUME_STANDARD = 0, DG_VOLUME_SPLIT = 1 };
 
 /* Box-side boundary types.  DG_BC_WALL: slip wall, the Rusanov flux against

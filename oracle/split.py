@@ -88,10 +88,12 @@ class SplitOperator(Operator):
     """L(U) with the split-form volume integral and the strong-form surface
     lift; surface="rusanov" (the solver's interface flux) or "ec" (the
     two-point flux itself at the interfaces, for the entropy-conservation
-    check).  Euler physics, conforming or 2:1 mortar meshes."""
+    check).  Euler physics, conforming or 2:1 mortar meshes; with viscous=
+    (mu, prandtl, gamma) the BR1 viscous terms of the standard operator are
+    added unchanged (Navier-Stokes, the paper's Taylor-Green setting)."""
 
-    def __init__(self, mesh, phys, surface="rusanov"):
-        super().__init__(mesh, phys)
+    def __init__(self, mesh, phys, surface="rusanov", viscous=None):
+        super().__init__(mesh, phys, viscous=viscous)
         if surface not in ("rusanov", "ec"):
             raise ValueError(surface)
         self.surface = surface

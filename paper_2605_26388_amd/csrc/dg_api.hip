@@ -614,8 +614,8 @@ int dg_create(const dg_desc* desc, dg_ctx** out) {
     return fail(DG_ERR_UNSUPPORTED, "positivity floor: Euler and Navier-Stokes physics only");
   if (d.volume != DG_VOLUME_STANDARD && d.volume != DG_VOLUME_SPLIT)
     return fail(DG_ERR_ARG, "volume must be DG_VOLUME_STANDARD or DG_VOLUME_SPLIT");
-  if (d.volume == DG_VOLUME_SPLIT && d.physics != DG_EULER)
-    return fail(DG_ERR_UNSUPPORTED, "split-form volume integral: Euler physics only");
+  if (d.volume == DG_VOLUME_SPLIT && d.physics != DG_EULER && d.physics != DG_NAVIER_STOKES)
+    return fail(DG_ERR_UNSUPPORTED, "split-form volume integral: Euler and Navier-Stokes physics only");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(DG_ERR_HIP, "no HIP device");
   if (d.device < 0 || d.device >= ndev) return fail(DG_ERR_ARG, "device ordinal out of range");

@@ -19,9 +19,17 @@
 // Closure: non-dimensional R = 1 so T = p / rho; Newtonian stress with the
 // Stokes hypothesis; q = -k grad T with k = gamma mu / (Pr (gamma - 1)).
 // LDS operands stay in double for both state precisions.
+//
+// Split form (SPLIT, eq. vol_split with the BR1 terms added, the paper's
+// Taylor-Green setting): pass 2 stages only -F_v^l for the D-sweep and the
+// primitives of the two-point flux, the inviscid volume term is the split sum
+// -2 (2/h_l) sum_m D_im F#_l(U_i, U_m) of the inviscid stage kernel (its m = i
+// term added on the face lanes with the own physical flux), and the surfaces
+// are unchanged.
 #include <type_traits>
 
 #include "dg_device.hpp"
+#include "dg_split.hpp"
 
 namespace dg {
 
@@ -62,16 +70,19 @@ __device__ __forceinline__ void visc_flux(const double (&W)[4], const double (&S
   Fv[3] = e;
 }
 
-template <int N, typename T, int PASS>
+template <int N, typename T, int PASS, bool SPLIT = false>
 __global__ void __launch_bounds__((Shape<3, N>::BS))
 k_ns(StageParams sp, MeshView mv, PhysConst pc, T* face) {
   using S = Shape<3, N>;
   constexpr int n = S::n, NP = S::NP, NF = S::NF, EPB = S::EPB, NV = 5;
   using PHYS = EulerPhys<3>;
+  constexpr bool SPL = SPLIT && PASS == 2;
 
   __shared__ double sW[4][EPB * NP];
   __shared__ double sF[PASS == 2 ? 3 : 1][NV][PASS == 2 ? EPB * NP : 1];
   __shared__ double sD[n * n];
+  __shared__ double sQ[SPL ? 8 : 1][SPL ? EPB * NP : 1];  // split form: rho/2, v/2, p, rho/(2p), ln rho, ln(rho/p)
+  __shared__ int sFar;
 
   const int tid = threadIdx.x;
   // the lane's entry of D, written to LDS only before the first barrier
@@ -200,21 +211,73 @@ k_ns(StageParams sp, MeshView mv, PhysConst pc, T* face) {
     double vel[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) vel[d] = u[1 + d] * th.ri;
+    SplitNode<3> own;
     if (tid < S::NT) {
 #pragma unroll
       for (int l = 0; l < 3; ++l) {
         double F[NV], Fv[4];
-        PHYS::flux(u, vel[l], th.p, l, F);
         visc_flux(W, Sg, l, mu, kc, Fv);
-        sF[l][0][tid] = F[0];
+        if constexpr (SPL) {
+          sF[l][0][tid] = 0.0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) sF[l][1 + q][tid] = F[1 + q] - Fv[q];
+          for (int q = 0; q < 4; ++q) sF[l][1 + q][tid] = -Fv[q];
+        } else {
+          PHYS::flux(u, vel[l], th.p, l, F);
+          sF[l][0][tid] = F[0];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) sF[l][1 + q][tid] = F[1 + q] - Fv[q];
+        }
       }
+    }
+    if constexpr (SPL) {
+      own.hr = 0.5 * u[0];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        own.v[d] = vel[d];
+        own.hv[d] = 0.5 * vel[d];
+      }
+      own.p = th.p;
+      own.hp = 0.5 * th.p;
+      own.hb = 0.5 * (u[0] * frcp(th.p));
+      if (tid < S::NT) {
+        sQ[0][tid] = own.hr;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) sQ[1 + d][tid] = own.hv[d];
+        sQ[4][tid] = own.p;
+        sQ[5][tid] = own.hb;
+      }
+      if (tid == 0) sFar = 0;
     }
     __syncthreads();
     double acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    if constexpr (SPL) {
+      // inviscid volume term: the split sum (the exact log means for the
+      // lanes with a far pair, as in the inviscid stage kernel)
+      const double gm1i = 1.0 / gm1;
+      bool far = false;
+      if (tid < S::NT) {
+        if constexpr (S::BS == 64)
+          split_sweep_pairs<3, N, 0>(tid, ii, stride, own, sQ, sD, g, gm1i, far, acc);
+        else
+          split_sweep<3, N, 0, false>(tid, ii, stride, own, sQ, sD, g, gm1i, far, acc);
+      }
+      if (far) sFar = 1;
+      __syncthreads();
+      if (sFar) {
+        if (tid < S::NT) {
+          sQ[6][tid] = log(u[0]);
+          sQ[7][tid] = log(2.0 * own.hb);
+        }
+        __syncthreads();
+        if (far) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+          split_sweep<3, N, 0, true>(tid, ii, stride, own, sQ, sD, g, gm1i, far, acc);
+        }
+      }
+    }
     if (tid < S::NT) {
 #pragma unroll
       for (int l = 0; l < 3; ++l) {
@@ -273,6 +336,12 @@ k_ns(StageParams sp, MeshView mv, PhysConst pc, T* face) {
         acc[0] = fma(sc, Dv[0], acc[0]);
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[1 + c] = fma(sc, Dv[1 + c] - (fvn_l[c] - fvo_l[c]), acc[1 + c]);
+        if constexpr (SPL) {
+          // the split sum's m = i term, 2 D_ii F_l(U_i)
+          const double cd = -2.0 * g[l] * sD[ii[l] * (n + 1)];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) acc[v] = fma(cd, Fo[v], acc[v]);
+        }
       }
     }
     if (active) {
@@ -319,7 +388,10 @@ static hipError_t ns_go(const Ctx& c, const StageParams& sp, hipStream_t s) {
   hipLaunchKernelGGL((k_ns<N, T, 1>), dim3(nblk), dim3(SH::BS), 0, s, sp, mesh_view(c), c.pc, face);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_ns<N, T, 2>), dim3(nblk), dim3(SH::BS), 0, s, sp, mesh_view(c), c.pc, face);
+  if (c.desc.volume == DG_VOLUME_SPLIT)
+    hipLaunchKernelGGL((k_ns<N, T, 2, true>), dim3(nblk), dim3(SH::BS), 0, s, sp, mesh_view(c), c.pc, face);
+  else
+    hipLaunchKernelGGL((k_ns<N, T, 2>), dim3(nblk), dim3(SH::BS), 0, s, sp, mesh_view(c), c.pc, face);
   return hipGetLastError();
 }
 

@@ -28,7 +28,7 @@ def make_pair(dim, N, nel, lo, hi, physics="euler", precision="f64", batch=1, pa
         if physics == "navier_stokes":
             viscous = dict(mu=mu, prandtl=prandtl, gamma=1.4)
     if volume == "split":
-        op = SplitOperator(mesh, phys)
+        op = SplitOperator(mesh, phys, viscous=viscous)
     else:
         op = Operator(mesh, phys, viscous=viscous)
     s = Solver(dim, N, nel, lo, hi, physics=physics, precision=precision, batch=batch,

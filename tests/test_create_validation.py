@@ -73,7 +73,8 @@ def create(d):
     # just above the 32-bit state addressing limit: 119^3 elements x 64 nodes x 5 x 8 B > 4 GiB
     (dict(nel=(119, 119, 119)), _abi.DG_ERR_UNSUPPORTED, "4 GiB"),
     (dict(volume=2), _abi.DG_ERR_ARG, "volume"),
-    (dict(volume=_abi.DG_VOLUME_SPLIT, physics=_abi.DG_NAVIER_STOKES), _abi.DG_ERR_UNSUPPORTED, "split"),
+    (dict(volume=_abi.DG_VOLUME_SPLIT, physics=_abi.DG_REACTING_EULER, dim=2, nel=(8, 8), mech="air5"),
+     _abi.DG_ERR_UNSUPPORTED, "split"),
     (dict(rho_floor=-1e-6), _abi.DG_ERR_ARG, "floor"),
     (dict(p_floor=float("nan")), _abi.DG_ERR_ARG, "floor"),
     (dict(p_floor=float("inf")), _abi.DG_ERR_ARG, "floor"),

@@ -15,7 +15,7 @@ import torch
 import dginputs as di
 from oracle.timestep import rk_stage
 from helpers import (make_pair, to_gpu, from_gpu, rel_err, random_euler_state, smooth_euler_state, rounding_spread,
-                     spread_err)
+                     spread_err, SPREAD_FACTOR)
 
 pytestmark = pytest.mark.gpu
 TOL64 = 1e-12
@@ -167,5 +167,47 @@ def test_split_rejected_where_unsupported():
         s.rhs_adjoint(U, s.empty())
     assert e.value.code == DG_ERR_UNSUPPORTED
     with pytest.raises(DGError) as e:
-        Solver(3, 3, (2, 2, 2), (0, 0, 0), (1, 1, 1), physics="navier_stokes", mu=1e-3, volume="split")
+        Solver(2, 3, (4, 4), (0, 0), (1, 1), physics="reacting", mech=di.preset_mechanism(di.PRESETS["air5_2d"]),
+               volume="split")
     assert e.value.code == DG_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("N", [2, 3, 4])
+def test_split_navier_stokes_rhs_parity_small(N):
+    """Split form with the BR1 viscous terms (the paper's Taylor-Green
+    setting) on a rough state, N = 2, 3, 4 (one- and two-wave elements)."""
+    op, s = make_pair(3, N, (3, 4, 3), (0, 0, 0), (1.0, 1.2, 0.9), physics="navier_stokes",
+                      mu=2e-2, prandtl=0.72, volume="split")
+    U = random_euler_state(op, 70 + N)
+    ref = op.rhs(U)
+    got = from_gpu(op, s.rhs(to_gpu(s, U)))
+    assert rel_err(got, ref) < TOL64
+
+
+def test_split_navier_stokes_tgv_full_workload():
+    """The Taylor-Green workload (16^3, N = 4) with the split form: dU/dt
+    within 1e-12 of each variable's norm or 16 oracle rounding spreads, the
+    stage built on it, and conservation."""
+    P = di.PRESETS["tgv3d"]
+    op, s = make_pair(3, P["N"], P["nel"], P["lo"], P["hi"], physics="navier_stokes", mu=P["mu"],
+                      prandtl=P["prandtl"], volume="split")
+    U = torch.tensor(di.taylor_green(op.mesh.coords(), mach=P["mach"]))[None]
+    Ug = to_gpu(s, U)
+    ref, spread = rounding_spread(op.rhs, U, P["nel"], [(0,), (1,), (2,)], cycles=True)
+    dU = s.rhs(Ug)
+    err = spread_err(from_gpu(op, dU), ref, spread)
+    print(f"split + BR1 TGV 16^3 N=4: spread {spread.numpy()}, err/bound {err:.3f}", flush=True)
+    assert err < 1.0
+    dt = s.dt_cfl(Ug, P["cfl"])
+    out = s.empty()
+    s.rk_stage(None, Ug, out, 0.0, 1.0, dt)
+    # the stage adds dt L to U (whose z-momentum is zero): its rounding plus
+    # dt times the right-hand side's bound
+    floor = dt * SPREAD_FACTOR * spread + 2.0 ** -52 * U.reshape(1, 5, -1).abs().amax(dim=(0, 2))
+    assert spread_err(from_gpu(op, out), U + dt * ref, floor / SPREAD_FACTOR) < 1.0
+    I = s.integrals(dU)[:, :-1]
+    vol = float(np.prod(np.subtract(P["hi"], P["lo"])))
+    from helpers import flux_scale
+    scale = np.maximum(s.integrals(dU.abs())[:, :-1], vol * flux_scale(op, U).numpy()[None])
+    assert np.abs(I / scale).max() < 1e-13
+    assert s.status()["nonphysical"] == 0
