@@ -34,19 +34,20 @@ __device__ __forceinline__ double wave_sound(const Thermo& t) {
 // (x + y) Q(u) / 2 with Q = 1/P = 1 - u/3 - 4u^2/45 - 44u^3/945 - ... (the
 // coefficients of the reciprocal power series, exact rationals below): no
 // cancellation as x -> y, the limit x at x = y comes out exactly, and no
-// division.  For u < 1e-2 (x/y within about 1.22) the series through u^7
-// leave a relative truncation below 1e-18.  The fast form uses the series for
-// every pair and raises `far` where u >= 1e-2; the exact form takes the
-// closed form there, with ln x and ln y read from LDS.  Branches inside the
-// unrolled sweep would make it spill registers, so a lane that raised `far`
-// redoes its whole volume sum in the exact form (a path smooth states never
-// take; the logarithms are only computed when some lane of the block needs
-// them).
+// division.  For u < SERIES_U_MAX = 1e-3 (x/y within about 1.065) the series
+// through u^4 leave a relative truncation below 1e-16 (P: u^5 / 11; Q: its
+// next coefficient 10196/467775 times u^5); smooth states stay far below (the
+// 32^3 benchmark state: u <= 4e-5 for every pair of every line).  The fast
+// form uses the series for every pair and raises `far` where u >=
+// SERIES_U_MAX; the exact form takes the closed form there, with ln x and ln y
+// read from LDS.  Branches inside the unrolled sweep would make it spill
+// registers, so a lane that raised `far` redoes its whole volume sum in the
+// exact form (a path smooth states never take; the logarithms are only
+// computed when some lane of the block needs them).
+constexpr double SERIES_U_MAX = 1e-3;
+
 __device__ __forceinline__ double atanh_ratio_series(double u) {  // P(u)
-  double P = 1.0 / 15.0;
-  P = fma(P, u, 1.0 / 13.0);
-  P = fma(P, u, 1.0 / 11.0);
-  P = fma(P, u, 1.0 / 9.0);
+  double P = 1.0 / 9.0;
   P = fma(P, u, 1.0 / 7.0);
   P = fma(P, u, 1.0 / 5.0);
   P = fma(P, u, 1.0 / 3.0);
@@ -54,10 +55,7 @@ __device__ __forceinline__ double atanh_ratio_series(double u) {  // P(u)
 }
 
 __device__ __forceinline__ double inv_atanh_ratio_series(double u) {  // Q(u) = 1 / P(u)
-  double Q = -25865068.0 / 1915538625.0;
-  Q = fma(Q, u, -10719068.0 / 638512875.0);
-  Q = fma(Q, u, -10196.0 / 467775.0);
-  Q = fma(Q, u, -428.0 / 14175.0);
+  double Q = -428.0 / 14175.0;
   Q = fma(Q, u, -44.0 / 945.0);
   Q = fma(Q, u, -4.0 / 45.0);
   Q = fma(Q, u, -1.0 / 3.0);
@@ -75,9 +73,9 @@ __device__ __forceinline__ double log_mean(double hx, double hy, const double* l
   const double u = f * f;
   double r = hs * inv_atanh_ratio_series(u);
   if constexpr (EXACT) {
-    if (u >= 1e-2) r = 2.0 * hd / (*lnx - *lny);
+    if (u >= SERIES_U_MAX) r = 2.0 * hd / (*lnx - *lny);
   } else {
-    far |= u >= 1e-2;
+    far |= u >= SERIES_U_MAX;
   }
   return r;
 }
@@ -90,9 +88,9 @@ __device__ __forceinline__ double inv_log_mean(double hx, double hy, const doubl
   const double u = f * f;
   double r = atanh_ratio_series(u) * rs;
   if constexpr (EXACT) {
-    if (u >= 1e-2) r = (*lnx - *lny) / (2.0 * hd);
+    if (u >= SERIES_U_MAX) r = (*lnx - *lny) / (2.0 * hd);
   } else {
-    far |= u >= 1e-2;
+    far |= u >= SERIES_U_MAX;
   }
   return r;
 }
