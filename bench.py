@@ -38,13 +38,13 @@ def split_flops_per_element(dim, N):
     """Algorithmic FP64 operations of the split-form volume sum of one
     element (an FMA counts 2): one two-point flux per unordered node pair of
     every line (the flux is symmetric), each pair adding D_im F# to node i and
-    D_mi F# to node m.  The flux as evaluated: two log means (30 and 25
-    operations: sum, difference, a reciprocal of 5, the degree-7 series, a
-    second reciprocal or the products), arithmetic means and v_i . v_m
-    (4 dim - 1), and the rows (13 + dim), i.e. 67 + 5 dim; plus 2 x (dim + 2)
+    D_mi F# to node m.  The flux as evaluated: two log means (24 and 19
+    operations: sum, difference, a reciprocal of 5, the series through u^4,
+    a second reciprocal or the products), arithmetic means and v_i . v_m
+    (4 dim - 1), and the rows (13 + dim), i.e. 55 + 5 dim; plus 2 x (dim + 2)
     FMAs of accumulation."""
     n = N + 1
-    flux = 67 + 5 * dim
+    flux = 55 + 5 * dim
     acc = 2 * 2 * (dim + 2)
     lines = dim * n ** (dim - 1)
     return lines * (n * (n - 1) // 2) * (flux + acc)
@@ -207,7 +207,7 @@ def kernel_source_hash():
     """sha256 over the sources the headline stage kernel is compiled from."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("k_stage.hip", "dg_device.hpp", "dg_internal.hpp"):
+    for f in ("k_stage.hip", "dg_device.hpp", "dg_internal.hpp", "dg_split.hpp"):
         with open(os.path.join(ROOT, "paper_2605_26388_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()

@@ -17,11 +17,11 @@ import bench  # noqa: E402
 
 
 def test_split_flop_count_per_element():
-    # 3 directions x 16 lines x 6 unordered pairs x (82 + 20) operations
-    assert bench.split_flops_per_element(3, 3) == 3 * 16 * 6 * 102 == 29376
-    # 2-D, N = 1: 2 directions x 2 lines x 1 pair x (77 + 16)
-    assert bench.split_flops_per_element(2, 1) == 2 * 2 * 1 * 93
-    assert abs(bench.split_flops_per_element(3, 3) * 32 ** 3 / 1e9 - 0.963) < 1e-3
+    # 3 directions x 16 lines x 6 unordered pairs x (70 + 20) operations
+    assert bench.split_flops_per_element(3, 3) == 3 * 16 * 6 * 90 == 25920
+    # 2-D, N = 1: 2 directions x 2 lines x 1 pair x (65 + 16)
+    assert bench.split_flops_per_element(2, 1) == 2 * 2 * 1 * 81
+    assert abs(bench.split_flops_per_element(3, 3) * 32 ** 3 / 1e9 - 0.849) < 1e-3
 
 
 def test_traffic_follows_the_committed_counters():
