@@ -479,6 +479,20 @@ MeshView mesh_view(const Ctx& c) {
     if (sh >= 0) {
       m.zf_shift = sh;
       m.zf_plane = c.desc.nel[0] * c.desc.nel[1];
+      // x tiles of 16 columns where nx is 16 times a power of two of at
+      // least 4 (64, 128, ... columns): the y-neighbour then stays within
+      // 2^sh * 16 blocks.  Measured at 64^3, FP64, 4 z-planes per group: the
+      // bytes fetched from beyond L2 fall from 2.4x to 1.4x of the
+      // algorithmic bytes in stage 1 and from 1.5x to 1.2x in stages 2 and
+      // 3; tiles of 8 columns fetch as much and run slower, and on 32
+      // columns the plain groups fetch less than tiles of 16.
+      constexpr int TXS = 4;
+      const int nx = c.desc.nel[0], nh = nx >> TXS;
+      if (nx % (1 << TXS) == 0 && nh >= 4 && (nh & (nh - 1)) == 0) {
+        m.zf_txs = TXS;
+        m.zf_nhs = __builtin_ctz((unsigned)nh);
+        m.zf_nx = nx;
+      }
     }
   }
   return m;

@@ -45,10 +45,15 @@ __device__ __forceinline__ int xcd_remap(int w, int nblocks) {
 // in time, beyond what the XCD's L2 keeps while the other streams of the
 // stage pass through it; taking groups of dz whole z-planes with z fastest
 // (then x, then y) brings the z-neighbour to the adjacent block and the x- and
-// y-neighbours to within dz and dz*nx blocks.  Only for one element per block
-// (the block index is the element index); a bijection of [0, E) when dz
-// divides nz, which the host ensures.  The Cartesian stage kernel uses it
-// (measured: 16 % fewer bytes fetched, 1 % faster); the curvilinear,
+// y-neighbours to within dz and dz*nx blocks.  On wide meshes dz*nx is itself
+// too far (the y-neighbour's lines are evicted before they are used again):
+// there the group's columns are cut into tiles of tx = 2^zf_txs, each tile
+// taken whole (z fastest, then x inside the tile, then y) before the next, so
+// that the y-neighbour is dz*tx blocks away and only the x-neighbours across
+// a tile edge are far.  Only for one element per block (the block index is
+// the element index); a bijection of [0, E) when dz divides nz and the tiles
+// divide nx, which the host ensures.  The Cartesian stage kernel uses it
+// (measured at 32^3: 16 % fewer bytes fetched, 1 % faster); the curvilinear,
 // Navier-Stokes and adjoint kernels, which stream more arrays per element,
 // measured 1-2 % slower with it and keep the plain order.
 template <int EPB>
@@ -59,8 +64,17 @@ __device__ __forceinline__ int zfast_block(int eb, const MeshView& mv) {
     if (mv.zf_plane == 0) return eb;
     const unsigned dz = 1u << mv.zf_shift;
     const unsigned G = dz * (unsigned)mv.zf_plane;
-    const unsigned g = (unsigned)eb / G, t = (unsigned)eb - g * G;
-    return (int)(g * G + (t & (dz - 1)) * (unsigned)mv.zf_plane + (t >> mv.zf_shift));
+    if (mv.zf_txs == 0) {
+      const unsigned g = (unsigned)eb / G, t = (unsigned)eb - g * G;
+      return (int)(g * G + (t & (dz - 1)) * (unsigned)mv.zf_plane + (t >> mv.zf_shift));
+    }
+    // block ordinal = ((g * nh + h) * ny + y) * tx * dz + xl * dz + zl
+    const unsigned Gs = G >> mv.zf_nhs;  // one tile of one group
+    const unsigned sg = (unsigned)eb / Gs, t = (unsigned)eb - sg * Gs;
+    const unsigned g = sg >> mv.zf_nhs, h = sg & ((1u << mv.zf_nhs) - 1u);
+    const unsigned zl = t & (dz - 1), xl = (t >> mv.zf_shift) & ((1u << mv.zf_txs) - 1u);
+    const unsigned y = t >> (mv.zf_shift + mv.zf_txs);
+    return (int)(g * G + zl * (unsigned)mv.zf_plane + y * (unsigned)mv.zf_nx + (h << mv.zf_txs) + xl);
   }
 }
 
@@ -87,20 +101,29 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void* base, size_t bytes) {
 // Element index i within the descriptor's range; the optional soff is a
 // uniform byte offset (e.g. of a variable plane) added in a scalar register.
 template <typename T> struct Buf;
+// CPOL: the instruction's cache-policy bits (0: default; CPOL_NT: the
+// non-temporal hint, for streams that no other workgroup reads again soon).
+constexpr int CPOL_NT = 2;
 template <> struct Buf<double> {
+  template <int CPOL = 0>
   static __device__ __forceinline__ double load(rsrc_t r, unsigned i, unsigned soff = 0) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, i * 8u, soff, 0));
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, i * 8u, soff, CPOL));
   }
+  template <int CPOL = 0>
   static __device__ __forceinline__ void store(rsrc_t r, unsigned i, double x, unsigned soff = 0) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, i * 8u, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, i * 8u, soff, CPOL);
   }
 };
 template <> struct Buf<float> {
+  template <int CPOL = 0>
   static __device__ __forceinline__ double load(rsrc_t r, unsigned i, unsigned soff = 0) {
-    return static_cast<double>(__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, i * 4u, soff, 0)));
+    return static_cast<double>(
+        __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, i * 4u, soff, CPOL)));
   }
+  template <int CPOL = 0>
   static __device__ __forceinline__ void store(rsrc_t r, unsigned i, double x, unsigned soff = 0) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, static_cast<float>(x)), r, i * 4u, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, static_cast<float>(x)), r, i * 4u, soff,
+                                          CPOL);
   }
 };
 

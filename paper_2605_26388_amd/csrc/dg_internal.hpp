@@ -47,8 +47,11 @@ struct MeshView {
   unsigned long long* first_bad;
   // 3-D Cartesian meshes (lexicographic element order, x fastest): element
   // blocks are taken in groups of 2^zf_shift whole z-planes of zf_plane
-  // elements each, z fastest inside a group; zf_plane = 0 keeps the order
+  // elements each, z fastest inside a group; zf_plane = 0 keeps the order.
+  // zf_txs > 0: the group's x range (zf_nx columns) is cut into 2^zf_nhs
+  // tiles of 2^zf_txs columns, taken one after the other
   int zf_shift = 0, zf_plane = 0;
+  int zf_txs = 0, zf_nhs = 0, zf_nx = 0;
 };
 
 // One 2:1 non-conforming face (2-D): coarse element, direction, side of the

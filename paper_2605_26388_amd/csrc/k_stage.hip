@@ -413,12 +413,13 @@ __device__ __forceinline__ double lane0(double x) {
   return __builtin_bit_cast(double, r);
 }
 
-template <typename T>
+template <typename T, bool NT>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
 k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
   using PHYS = EulerPhys<3>;
   constexpr int DIM = 3, N = 3, n = 4, NP = 64, NV = 5;
   constexpr bool F32 = std::is_same<T, float>::value;
+  constexpr int CP = NT ? CPOL_NT : 0;  // policy of the streams no other workgroup reads: U0 and the output
   constexpr int WPV = F32 ? 32 : 64;  // dwords of face data per direction and variable
   __shared__ T sF[NV][NP];
   __shared__ T sDg[DIM][n * n];
@@ -477,13 +478,13 @@ k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
   if (!F32 && use_u0) {
     const rsrc_t r0 = make_rsrc(static_cast<const T*>(sp.U0) + (size_t)b * NV * plane, abytes);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) u0r[v] = Buf<T>::load(r0, off, v * pstride);
+    for (int v = 0; v < NV; ++v) u0r[v] = Buf<T>::template load<CP>(r0, off, v * pstride);
   }
   if (F32 && use_u0) {  // FP32: U0 into LDS
     const rsrc_t r0 = make_rsrc(static_cast<const T*>(sp.U0) + (size_t)b * NV * plane, abytes);
 #pragma unroll
     for (int v = 0; v < NV; ++v)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(r0, DG_LDS_PTR(&sU0[v][0]), 4, off * 4u, v * pstride, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(r0, DG_LDS_PTR(&sU0[v][0]), 4, off * 4u, v * pstride, 0, CP);
   }
 
   Thermo th;
@@ -557,7 +558,7 @@ k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
   const rsrc_t ro = make_rsrc(static_cast<T*>(sp.out) + (size_t)b * NV * plane, abytes);
   if (sp.mode == 0) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Buf<T>::store(ro, off, acc[v], v * pstride);
+    for (int v = 0; v < NV; ++v) Buf<T>::template store<CP>(ro, off, acc[v], v * pstride);
     return;
   }
   T r[NV];
@@ -579,7 +580,7 @@ k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
     }
   }
 #pragma unroll
-  for (int v = 0; v < NV; ++v) Buf<T>::store(ro, off, r[v], v * pstride);
+  for (int v = 0; v < NV; ++v) Buf<T>::template store<CP>(ro, off, r[v], v * pstride);
   if (sp.mode == 2) {  // second combination of the same L(Uk), no floor
     const rsrc_t r2 = make_rsrc(static_cast<T*>(sp.out2) + (size_t)b * NV * plane, abytes);
     const bool use_v = sp.a2 != 0.0;
@@ -660,13 +661,24 @@ k_mortar(const MortarRec* recs, const T* U, MeshView mv, PhysConst pc) {
 // ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
+// the Infinity Cache (MALL) of the device: 256 MiB
+constexpr size_t NT_STATE_BYTES = (size_t)256 << 20;
+
 template <int DIM, int N, class PHYS, typename T, bool MORTAR, bool SPLIT>
 static hipError_t go(const Ctx& c, const StageParams& sp, hipStream_t s) {
   using SH = Shape<DIM, N>;
   const int nEB = (c.E + SH::EPB - 1) / SH::EPB;
   const int nblk = nEB * c.B;
   if constexpr (DIM == 3 && N == 3 && std::is_same<PHYS, EulerPhys<3>>::value && !MORTAR && !SPLIT) {
-    hipLaunchKernelGGL(k_stage_n3<T>, dim3(nblk), dim3(64), 0, s, sp, mesh_view(c), c.pc);
+    // states larger than the Infinity Cache are not read back from it by the
+    // next stage: there the non-temporal hint keeps U0 and the output from
+    // displacing the neighbour faces in L2 (at cache-resident sizes it would
+    // send the output past the cache the next stage reads it from)
+    const size_t state_bytes = (size_t)c.B * 5 * c.E * 64 * sizeof(T);
+    if (state_bytes > NT_STATE_BYTES)
+      hipLaunchKernelGGL((k_stage_n3<T, true>), dim3(nblk), dim3(64), 0, s, sp, mesh_view(c), c.pc);
+    else
+      hipLaunchKernelGGL((k_stage_n3<T, false>), dim3(nblk), dim3(64), 0, s, sp, mesh_view(c), c.pc);
     return hipGetLastError();
   }
   hipLaunchKernelGGL((k_stage<DIM, N, PHYS, T, MORTAR, SPLIT>), dim3(nblk), dim3(SH::BS), 0, s, sp, mesh_view(c),

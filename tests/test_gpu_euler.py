@@ -33,16 +33,60 @@ def test_rhs_parity_all_degrees(dim, N):
 
 
 @pytest.mark.parametrize("N,nel", [(3, (3, 2, 2)), (3, (2, 3, 6)), (3, (3, 3, 4)), (3, (2, 2, 8)), (5, (3, 2, 2)),
-                                   (4, (2, 3, 4))])
+                                   (4, (2, 3, 4)), (3, (64, 2, 4)), (3, (128, 3, 2))])
 def test_rhs_parity_block_orders(N, nel):
     """3-D meshes whose z-count selects each order of the element blocks
     (groups of 2 or 4 z-planes taken z fastest; plain order for odd counts is
-    covered above), batched so that a group boundary falls between members."""
+    covered above; 64 and 128 columns in x cut the groups into tiles of 16
+    columns), batched so that a group boundary falls between members."""
     op, s = make_pair(3, N, nel, (0.0, 0.0, 0.0), (1.0, 0.8, 1.2), batch=2)
     U = random_euler_state(op, 40 + N, B=2)
     ref = op.rhs(U)
     got = from_gpu(op, s.rhs(to_gpu(s, U)))
     assert rel_err(got, ref) < TOL64
+
+
+def _tile4(X, n16=16):
+    """A (B, nv, E, Np) state of a 16^3 mesh repeated 4 times along each
+    element axis (lexicographic element order, x fastest)."""
+    B, nv, _, Np = X.shape
+    Y = X.reshape(B, nv, n16, n16, n16, Np).repeat(1, 1, 4, 4, 4, 1)
+    return Y.reshape(B, nv, -1, Np).contiguous()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_64cubed_as_tiled_16cubed(precision):
+    """64^3, N = 3: states beyond the 256 MiB Infinity Cache, where the stage
+    kernel takes the non-temporal cache policy for U0 and the output and
+    cuts the element groups into tiles of 16 columns.  A state that repeats
+    a 16^3 state 4 times along each axis, on a box 4 times as long (the same
+    element sizes, the same arithmetic per element), must give the 16^3
+    right-hand side and stage output repeated, bit for bit; the 16^3 FP64
+    right-hand side itself is checked against the oracle."""
+    from paper_2605_26388_amd import Solver
+    op, s16 = make_pair(3, 3, (16, 16, 16), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), precision=precision)
+    U = random_euler_state(op, 77)
+    U0 = random_euler_state(op, 78)
+    g16, g016 = to_gpu(s16, U), to_gpu(s16, U0)
+    d16 = s16.rhs(g16)
+    if precision == "f64":
+        assert rel_err(from_gpu(op, d16), op.rhs(U)) < TOL64
+    o16 = s16.empty()
+    s16.rk_stage(g016, g16, o16, 0.75, 0.25, 0.0025)
+    d16, o16 = d16.cpu(), o16.cpu()
+    del g16, g016
+    s16.close()
+    s64 = Solver(3, 3, (64, 64, 64), (0.0, 0.0, 0.0), (4.0, 4.0, 4.0), precision=precision)
+    g64 = _tile4(U.reshape(1, 5, 4096, 64)).to(s64.device, s64.dtype)
+    g064 = _tile4(U0.reshape(1, 5, 4096, 64)).to(s64.device, s64.dtype)
+    d64 = s64.rhs(g64)
+    assert torch.equal(d64.cpu(), _tile4(d16))
+    del d64
+    o64 = s64.empty()
+    s64.rk_stage(g064, g64, o64, 0.75, 0.25, 0.0025)
+    assert torch.equal(o64.cpu(), _tile4(o16))
+    assert s64.status()["nonphysical"] == 0
+    s64.close()
 
 
 @pytest.mark.parametrize("dim", [2, 3])

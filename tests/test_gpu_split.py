@@ -123,12 +123,13 @@ def test_split_full_size_workload_parity():
     assert rel_err(from_gpu(op, out), ref_stage) < TOL64
 
 
-@pytest.mark.parametrize("nz", [2, 4])
-def test_split_block_orders_batched(nz):
+@pytest.mark.parametrize("nx,nz", [(5, 2), (5, 4), (64, 4)])
+def test_split_block_orders_batched(nx, nz):
     """3-D meshes whose z-count selects the element-block orders of the
-    stage kernel (groups of 2 and 4 whole z-planes taken z fastest), with a
-    batch of 2, through the pairwise split sweep."""
-    op, s = make_pair(3, 3, (5, 3, nz), (0, 0, 0), (TWO_PI,) * 3, batch=2, volume="split")
+    stage kernel (groups of 2 and 4 whole z-planes taken z fastest; 64
+    columns cut into tiles of 16), with a batch of 2, through the pairwise
+    split sweep."""
+    op, s = make_pair(3, 3, (nx, 3, nz), (0, 0, 0), (TWO_PI,) * 3, batch=2, volume="split")
     U = torch.cat([smooth_euler_state(op), random_euler_state(op, 40 + nz)])
     ref = op.rhs(U)
     got = from_gpu(op, s.rhs(to_gpu(s, U)))
