@@ -30,6 +30,15 @@ on the -xi_l face, and F* the Rusanov flux for the unnormalised normal n =
 Ja^l at the face node (each side uses its own node's Ja^l):
     F* = (F(U_L) + F(U_R)) . n / 2 - lam |n| (U_R - U_L) / 2,
     lam = max(|v_L . n^| + a_L, |v_R . n^| + a_R),  L on the -xi_l side.
+Split form (volume="split", eq. vol_split on curvilinear elements): the
+volume term becomes
+    J dU_i = -sum_l sum_m 2 D_im F#(U_i, U_m) . {{Ja^l}}_im - (lift as above),
+with Ranocha's two-point flux contracted with the average of the two nodes'
+contravariant vectors, {{Ja^l}}_im = (Ja^l_i + Ja^l_m) / 2 (the form whose
+conservation and entropy conservation rest on the discrete GCL above); the
+surface term is unchanged (F* - Ft^l(U_i) at face nodes).  surface="ec" puts
+the two-point flux itself at the interfaces, F#(U_L, U_R) . n with each side's
+own n, for the entropy check.
 Boundary faces (box sides that are not periodic), per type:
     wall     slip wall: ghost state with the normal velocity reversed,
              U_g = (rho, m - 2 (m . n^) n^, E), in the Rusanov flux (its mass
@@ -47,6 +56,7 @@ from .dgsem import dsweep, node_axis, trace
 from .mesh import cartesian_mesh
 from .physics import Euler
 from .refelem import gll
+from .split import ranocha_flux_n as split_ranocha_n
 
 
 def warp(X, lo, hi, A):
@@ -137,11 +147,31 @@ class CurvOperator:
     """L(U) for the Euler equations on a CurvMesh (strong form); bc_state is
     the prescribed conserved state of inflow sides."""
 
-    def __init__(self, mesh, gamma=1.4, bc_state=None):
+    def __init__(self, mesh, gamma=1.4, bc_state=None, volume="standard", surface="rusanov"):
+        if volume not in ("standard", "split") or surface not in ("rusanov", "ec"):
+            raise ValueError((volume, surface))
         self.mesh = mesh
         self.phys = Euler(mesh.dim, gamma)
         self.dim, self.N, self.n = mesh.dim, mesh.N, mesh.n
         self.bc_state = None if bc_state is None else torch.tensor(bc_state, dtype=torch.float64)
+        self.volume, self.surface = volume, surface
+
+    def split_volume(self, U):
+        """-sum_l sum_m 2 D_im F#(U_i, U_m) . (Ja^l_i + Ja^l_m) / 2 (times J)."""
+        m, dim = self.mesh, self.dim
+        out = torch.zeros_like(U)
+        for l in range(dim):
+            ax = node_axis(dim, l)
+            X = U.movedim(ax, -1)                                   # (B, nv, E, .., n) along l
+            n = X.shape[-1]
+            XL = X.unsqueeze(-1).expand(*X.shape, n)                # U_i at [.., i, m]
+            XR = X.unsqueeze(-2).expand(*X.shape[:-1], n, n)        # U_m at [.., i, m]
+            Ja = m.Ja[l].movedim(ax - 1, -1)                         # (dim, E, .., n)
+            Jav = [0.5 * (Ja[d].unsqueeze(-1) + Ja[d].unsqueeze(-2)) for d in range(dim)]
+            F = split_ranocha_n(XL, XR, Jav, self.phys.gamma)        # (B, nv, E, .., i, m)
+            s = torch.einsum("...im,im->...i", F, m.D)
+            out = out - 2.0 * s.movedim(-1, ax)
+        return out
 
     def _ft(self, F, Ja):
         """Ja . F: F list over d of (B, nv, ...), Ja (dim, ...) -> (B, nv, ...)."""
@@ -149,6 +179,8 @@ class CurvOperator:
 
     def _rusanov(self, UL, UR, n):
         """F* . n for states (B, nv, ...) and unnormalised normal n (dim, ...)."""
+        if self.surface == "ec":
+            return split_ranocha_n(UL, UR, [n[d][None] for d in range(self.dim)], self.phys.gamma)
         ph = self.phys
         PL, PR = ph.prims(UL), ph.prims(UR)
         FL = [ph.flux(UL, d, PL) for d in range(self.dim)]
@@ -183,9 +215,12 @@ class CurvOperator:
         P = ph.prims(U)
         F = [ph.flux(U, d, P) for d in range(dim)]
         Ft = [self._ft(F, m.Ja[l]) for l in range(dim)]
-        dU = torch.zeros_like(U)
-        for l in range(dim):
-            dU = dU - dsweep(Ft[l], m.D, dim, l)
+        if self.volume == "split":
+            dU = self.split_volume(U)
+        else:
+            dU = torch.zeros_like(U)
+            for l in range(dim):
+                dU = dU - dsweep(Ft[l], m.D, dim, l)
         winv = 1.0 / float(m.w[0])
         for l in range(dim):
             ax = node_axis(dim, l)

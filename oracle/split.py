@@ -66,6 +66,31 @@ def ranocha_flux(UL, UR, l, gamma):
     return torch.stack(rows, dim=1)
 
 
+def ranocha_flux_n(UL, UR, nvec, gamma):
+    """F#(U_L, U_R) . n for a direction field n (dim tensors broadcasting
+    against the states' node axes): the flux above is linear in the
+    direction, f_rho = {{rho}}_ln {{u}} . n, f_m_d = f_rho {{u_d}} + {{p}} n_d,
+    f_E = f_rho (1 / ((gamma - 1) {{rho/p}}_ln) + u_L . u_R / 2)
+          + (p_L u_R . n + p_R u_L . n) / 2;
+    n = e_l gives ranocha_flux along l."""
+    dim = UL.shape[1] - 2
+    rL, uL, pL = euler_prims(UL, gamma)
+    rR, uR, pR = euler_prims(UR, gamma)
+    rho_ln = log_mean(rL, rR)
+    b_ln = log_mean(rL / pL, rR / pR)
+    ua = [0.5 * (uL[d] + uR[d]) for d in range(dim)]
+    pa = 0.5 * (pL + pR)
+    f_rho = rho_ln * sum(ua[d] * nvec[d] for d in range(dim))
+    rows = [f_rho]
+    for d in range(dim):
+        rows.append(f_rho * ua[d] + pa * nvec[d])
+    uu = sum(uL[d] * uR[d] for d in range(dim))
+    uRn = sum(uR[d] * nvec[d] for d in range(dim))
+    uLn = sum(uL[d] * nvec[d] for d in range(dim))
+    rows.append(f_rho * (1.0 / ((gamma - 1.0) * b_ln) + 0.5 * uu) + 0.5 * (pL * uRn + pR * uLn))
+    return torch.stack(rows, dim=1)
+
+
 def split_volume(op, U):
     """-(2/J) sum_l sum_m D_im Ja^l F#_l(U_i, U_m) for every node."""
     dim, gamma = op.dim, op.phys.gamma

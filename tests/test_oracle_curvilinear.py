@@ -5,7 +5,12 @@ periodic meshes, the Jacobian against the analytic determinant of the warp
 (spectral convergence and the preserved area), vortex convergence on a warped
 mesh, slip walls (no mass or energy through them; a flow tangent to straight
 walls is steady) and supersonic inflow/outflow (a uniform supersonic stream is
-steady through curved boundaries)."""
+steady through curved boundaries).  The split form on curvilinear elements:
+the two-point flux along a vector against the Cartesian one and its
+linearity, reduction to the Cartesian split operator at zero warp, free
+stream, conservation and entropy conservation (EC interfaces) on warped
+meshes -- the last two failing when the pair's metrics are not averaged --
+and vortex convergence."""
 
 import math
 
@@ -170,3 +175,132 @@ def test_free_stream_far_from_the_origin(dim):
         c = uniform(m, 1.1, (0.3, -0.2, 0.1)[:dim], 0.9)
         res = float(op.rhs(c).abs().max()) / flux_scale(m, c)
         assert res < 2e-14, (off, res)
+
+
+# --- split form on curvilinear elements -------------------------------------------
+
+def _entropy_vars(U):
+    """d eta / dU for eta = -rho s / (gamma - 1), s = ln(p rho^-gamma)."""
+    rho, m, E = U[:, 0], U[:, 1:-1], U[:, -1]
+    u = m / rho[:, None]
+    p = (G - 1) * (E - 0.5 * (m * u).sum(1))
+    s = torch.log(p) - G * torch.log(rho)
+    w0 = (G - s) / (G - 1) - 0.5 * rho * (u * u).sum(1) / p
+    return torch.cat([w0[:, None], rho[:, None] * u / p[:, None], -(rho / p)[:, None]], 1)
+
+
+def test_ranocha_flux_along_a_vector_reduces_and_is_linear():
+    """F#(U_L, U_R) . n: n = e_l gives the Cartesian flux along l bit for bit,
+    and the flux is linear in n."""
+    from oracle.split import ranocha_flux, ranocha_flux_n
+    rng = np.random.default_rng(5)
+    def states(seed):
+        r = np.random.default_rng(seed)
+        return torch.tensor(di.conserved_from_primitive(r.uniform(0.5, 2, 50), [r.uniform(-1, 1, 50) for _ in range(3)],
+                                                        r.uniform(0.5, 2, 50), G))[None]
+    UL, UR = states(1), states(2)
+    for l in range(3):
+        e = [torch.full((50,), 1.0 if d == l else 0.0, dtype=torch.float64) for d in range(3)]
+        assert torch.equal(ranocha_flux_n(UL, UR, e, G), ranocha_flux(UL, UR, l, G))
+    n1 = [torch.tensor(rng.normal(size=50)) for _ in range(3)]
+    n2 = [torch.tensor(rng.normal(size=50)) for _ in range(3)]
+    a, b = 0.7, -1.3
+    lhs = ranocha_flux_n(UL, UR, [a * x + b * y for x, y in zip(n1, n2)], G)
+    rhs = a * ranocha_flux_n(UL, UR, n1, G) + b * ranocha_flux_n(UL, UR, n2, G)
+    assert float((lhs - rhs).abs().max()) < 1e-13 * float(rhs.abs().max())
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_split_zero_warp_equals_cartesian_split_operator(dim):
+    from oracle.split import SplitOperator
+    nel, lo, hi = ((4, 3), (0, 0), (1.0, 1.3)) if dim == 2 else ((3, 2, 3), (0, 0, 0), (1.0, 0.8, 1.2))
+    m = CurvMesh(dim, 3, nel, lo, hi, 0.0)
+    U = rand_state(m, 1)
+    a = CurvOperator(m, volume="split").rhs(U)
+    b = SplitOperator(cartesian_mesh(dim, 3, nel, lo, hi), Euler(dim)).rhs(U)
+    assert float((a - b).abs().max()) < 1e-13 * float(b.abs().max())
+
+
+def _split_volume_one_sided(op, U, side):
+    """The split volume term with the metrics of node i only (side 0) or of
+    node m only (side 1) instead of their average: planted mistakes."""
+    from oracle.dgsem import node_axis
+    from oracle.split import ranocha_flux_n
+    m, dim = op.mesh, op.dim
+    out = torch.zeros_like(U)
+    for l in range(dim):
+        ax = node_axis(dim, l)
+        X = U.movedim(ax, -1)
+        n = X.shape[-1]
+        XL = X.unsqueeze(-1).expand(*X.shape, n)
+        XR = X.unsqueeze(-2).expand(*X.shape[:-1], n, n)
+        Ja = m.Ja[l].movedim(ax - 1, -1)
+        Jav = [(Ja[d].unsqueeze(-1) if side == 0 else Ja[d].unsqueeze(-2)).expand(*Ja[d].shape, n)
+               for d in range(dim)]
+        F = ranocha_flux_n(XL, XR, Jav, G)
+        out = out - 2.0 * torch.einsum("...im,im->...i", F, m.D).movedim(-1, ax)
+    return out
+
+
+@pytest.mark.parametrize("dim,N", [(2, 2), (2, 4), (3, 2), (3, 3)])
+def test_split_free_stream_conservation_and_entropy_on_warped_mesh(dim, N):
+    """Warped periodic mesh: a constant state stays constant (discrete GCL);
+    sum J w dU/dt = 0 (the two-point flux with averaged metrics is
+    symmetric in its nodes); with the two-point flux at the interfaces the
+    entropy production sum J w w(U) . dU/dt is zero to rounding, and negative
+    with the Rusanov flux.  The metrics of one node only keep the free stream
+    but break conservation and entropy conservation."""
+    nel = (4, 3) if dim == 2 else (3, 3, 2)
+    lo, hi = (0.0,) * dim, (1.0, 1.2, 0.9)[:dim]
+    m = CurvMesh(dim, N, nel, lo, hi, 0.04)
+    op = CurvOperator(m, volume="split")
+    op_ec = CurvOperator(m, volume="split", surface="ec")
+    c = uniform(m, 1.1, (0.3, -0.2, 0.1)[:dim], 0.9)
+    assert float(op.rhs(c).abs().max()) < 1e-13 * flux_scale(m, c)
+    U = rand_state(m, 2 + N)
+    wJ = weights(m)
+    red = tuple(range(1, 1 + dim))
+
+    def cons(dU):
+        I = torch.stack([(wJ * dU[0, v]).sum(dim=(0,) + red) for v in range(dim + 2)])
+        S = torch.stack([(wJ * dU[0, v].abs()).sum(dim=(0,) + red) for v in range(dim + 2)])
+        return float((I.abs() / S).max())
+
+    W = _entropy_vars(U.reshape(1, dim + 2, -1)).reshape(U.shape)
+
+    def production(dU):
+        return float((wJ * (W * dU).sum(1)[0]).sum()), float((wJ * (W * dU).abs().sum(1)[0]).sum())
+
+    assert cons(op.rhs(U)) < 1e-13
+    p_ec, s_ec = production(op_ec.rhs(U))
+    assert abs(p_ec) < 1e-13 * s_ec
+    p_rs, s_rs = production(op.rhs(U))
+    assert p_rs < -1e-6 * s_rs
+    # planted: metrics of one node of each pair (3-D only: the 2-D warp keeps
+    # each Ja^l constant along its own lines, where the average is exact)
+    for side in ((0, 1) if dim == 3 else ()):
+        bad = op_ec.rhs(U) - op_ec.split_volume(U) / m.J[None, None] + _split_volume_one_sided(op_ec, U, side) / m.J[None, None]
+        p_bad, s_bad = production(bad)
+        assert cons(bad) > 1e-8 or abs(p_bad) > 1e-8 * s_bad
+
+
+def test_split_vortex_convergence_on_warped_mesh():
+    """The isentropic vortex advected to T = 0.5 on a warped periodic mesh
+    with the split form: the density error converges at the standard form's
+    rate (8^2 -> 16^2, N = 3)."""
+    errs = []
+    for nel in (8, 16):
+        m = CurvMesh(2, 3, (nel, nel), (-5, -5), (5, 5), 0.02)
+        op = CurvOperator(m, volume="split")
+        U = torch.tensor(di.vortex(m.coords(), 0.0))[None]
+        T = 0.5
+        h = 10.0 / nel
+        dt = 0.5 * h / (7 * op.lam_max(U))
+        nsteps = int(np.ceil(T / dt))
+        dt = T / nsteps
+        for _ in range(nsteps):
+            U = ssprk33_step(op, U, dt)
+        ex = torch.tensor(di.vortex(m.coords(), T))[None]
+        errs.append(float((U[:, 0] - ex[:, 0]).abs().max()))
+    order = math.log2(errs[0] / errs[1])
+    assert 2.8 < order < 5.5, (errs, order)
