@@ -247,4 +247,82 @@ __device__ __forceinline__ void split_sweep_pairs(int tid, const int (&ii)[3], c
   }
 }
 
+// The same two-point flux contracted with a direction vector nv (curvilinear
+// elements: nv = Ja^l_i + Ja^l_m, twice the pair's averaged contravariant
+// vector; the flux is linear in the direction):
+//   f_rho = {{rho}}_ln {{v}} . nv,  f_v_d = f_rho {{v_d}} + {{p}} nv_d,
+//   f_E = f_rho (1 / ((gamma - 1) {{beta}}_ln) + v_i . v_m / 2)
+//         + (p_i v_m . nv + p_m v_i . nv) / 2.
+template <int DIM, bool EXACT, int W>
+__device__ __forceinline__ void ranocha_flux_n(const SplitNode<DIM>& a, const double (*Q)[W], int i, int m,
+                                               const double (&nv)[DIM], double gm1i, bool& far,
+                                               double (&F)[DIM + 2]) {
+  const double hrm = Q[0][m], pm = Q[DIM + 1][m], hbm = Q[DIM + 2][m];
+  double hvm[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) hvm[d] = Q[1 + d][m];
+  const double rho_ln = log_mean<EXACT>(a.hr, hrm, &Q[DIM + 3][i], &Q[DIM + 3][m], far);
+  const double ib_ln = inv_log_mean<EXACT>(a.hb, hbm, &Q[DIM + 4][i], &Q[DIM + 4][m], far);
+  double va[DIM];
+  double hvv = a.v[0] * hvm[0];
+  double van = 0.0, hvmn = 0.0, hvin = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    va[d] = a.hv[d] + hvm[d];
+    if (d > 0) hvv = fma(a.v[d], hvm[d], hvv);
+    van = fma(va[d], nv[d], van);
+    hvmn = fma(hvm[d], nv[d], hvmn);
+    hvin = fma(a.hv[d], nv[d], hvin);
+  }
+  const double pa = fma(0.5, pm, a.hp);
+  const double fr = rho_ln * van;
+  F[0] = fr;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) F[1 + d] = fma(fr, va[d], pa * nv[d]);
+  F[DIM + 1] = fma(fr, fma(ib_ln, gm1i, hvv), fma(a.p, hvmn, pm * hvin));
+}
+
+// Split-form volume sum of one lane on curvilinear elements, directions
+// l..DIM-1: acc -= sum_{m != i} D_im F#(U_i, U_m) . (Ja^l_i + Ja^l_m), i.e.
+// -2 sum_m D_im F# . {{Ja^l}}_im, over the lane's line along l (partners i+1,
+// ..., i+N modulo n; the m = i term is added with the faces).  Ja[l][d] holds
+// the lane's own contravariant vectors, J rows the LDS copies of all nodes'.
+template <int DIM, int N, int l, bool EXACT, int W>
+__device__ __forceinline__ void split_sweep_curv(int tid, const int (&ii)[3], const int (&stride)[3],
+                                                 const SplitNode<DIM>& a, const double (*Q)[W],
+                                                 const double (*Jm)[W], const double (&Ja)[DIM][DIM],
+                                                 const double* sD, double gm1i, bool& far, double (&acc)[DIM + 2]) {
+  if constexpr (l < DIM) {
+    constexpr int NV = DIM + 2, n = N + 1;
+    const int il = ii[l];
+    const int st = stride[l];
+    const int base = tid - il * st;
+    double s[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) s[v] = 0.0;
+    auto term = [&](int k) {
+      const int mi = il + k < n ? il + k : il + k - n;
+      const int m = base + mi * st;
+      double nv[DIM];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) nv[d] = Ja[l][d] + Jm[l * DIM + d][m];
+      double F[NV];
+      ranocha_flux_n<DIM, EXACT>(a, Q, tid, m, nv, gm1i, far, F);
+      const double dim = sD[il * n + mi];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) s[v] = fma(dim, F[v], s[v]);
+    };
+    if constexpr (EXACT) {  // rare path: partner loop kept rolled
+#pragma unroll 1
+      for (int k = 1; k <= N; ++k) term(k);
+    } else {
+#pragma unroll
+      for (int k = 1; k <= N; ++k) term(k);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] -= s[v];
+    split_sweep_curv<DIM, N, l + 1, EXACT>(tid, ii, stride, a, Q, Jm, Ja, sD, gm1i, far, acc);
+  }
+}
+
 }  // namespace dg

@@ -20,9 +20,18 @@
 //      F* = Ft_own (no correction);
 //   4. dU = (volume + lift) / J, or the stage combination (positivity floor
 //      and dual output as the Cartesian stage).
+// Split form (SPLIT, eq. vol_split on curvilinear elements): step 2 stages
+// the primitives of the two-point flux and every node's Ja^l in LDS instead,
+// and the volume term is -sum_l sum_{m != i} D_im F#(U_i, U_m) . (Ja^l_i +
+// Ja^l_m), Ranocha's flux contracted with twice the pair's averaged
+// contravariant vector (the log means by the series of the Cartesian split
+// kernel, with the same exact redo for widely separated pairs); its m = i term
+// -2 D_ii Ft^l(U_i) is added on the face lanes, whose own flux Ft^l is then
+// evaluated in registers; the surface term is unchanged.
 #include <type_traits>
 
 #include "dg_device.hpp"
+#include "dg_split.hpp"
 
 namespace dg {
 
@@ -44,15 +53,19 @@ __device__ __forceinline__ void normal_flux(const double (&U)[DIM + 2], const do
   F[DIM + 1] = (U[DIM + 1] + p) * vn;
 }
 
-template <int DIM, int N>
+template <int DIM, int N, bool SPLIT>
 __global__ void __launch_bounds__((Shape<DIM, N>::BS)) __attribute__((amdgpu_waves_per_eu(3)))
 k_stage_curv(StageParams sp, MeshView mv, PhysConst pc, CurvArgs ca) {
   using S = Shape<DIM, N>;
   using PHYS = EulerPhys<DIM>;
   constexpr int n = S::n, NP = S::NP, EPB = S::EPB, NV = DIM + 2;
   constexpr bool UNIFORM_ELEM = (NP % 64) == 0;
+  constexpr int W = EPB * NP;
 
-  __shared__ double sF[DIM][NV][EPB * NP];
+  __shared__ double sF[SPLIT ? 1 : DIM][SPLIT ? 1 : NV][SPLIT ? 1 : W];
+  __shared__ double sQ[SPLIT ? DIM + 5 : 1][SPLIT ? W : 1];    // rho/2, v/2, p, rho/(2p), ln rho, ln(rho/p)
+  __shared__ double sJ[SPLIT ? DIM * DIM : 1][SPLIT ? W : 1];  // Ja^l_d of every node, row l*DIM + d
+  __shared__ int sFar;  // some lane of the block needs the exact log means
   __shared__ double sD[n * n];
 
   const int tid = threadIdx.x;
@@ -111,9 +124,32 @@ k_stage_curv(StageParams sp, MeshView mv, PhysConst pc, CurvArgs ca) {
 #pragma unroll
   for (int d = 0; d < DIM; ++d) vel[d] = u[1 + d] * th.ri;
 
-  // ---- contravariant fluxes in LDS -----------------------------------------
+  // ---- contravariant fluxes (split form: primitives and metrics) in LDS ------
   if (tid < n * n) sD[tid] = dval;
-  if (tid < S::NT) {
+  SplitNode<DIM> own;
+  if constexpr (SPLIT) {
+    own.hr = 0.5 * u[0];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      own.v[d] = vel[d];
+      own.hv[d] = 0.5 * vel[d];
+    }
+    own.p = th.p;
+    own.hp = 0.5 * th.p;
+    own.hb = 0.5 * (u[0] * frcp(th.p));
+    if (tid < S::NT) {
+      sQ[0][tid] = own.hr;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) sQ[1 + d][tid] = own.hv[d];
+      sQ[DIM + 1][tid] = own.p;
+      sQ[DIM + 2][tid] = own.hb;
+#pragma unroll
+      for (int l = 0; l < DIM; ++l)
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) sJ[l * DIM + d][tid] = Ja[l][d];
+    }
+    if (tid == 0) sFar = 0;
+  } else if (tid < S::NT) {
 #pragma unroll
     for (int l = 0; l < DIM; ++l) {
       double F[NV];
@@ -128,7 +164,25 @@ k_stage_curv(StageParams sp, MeshView mv, PhysConst pc, CurvArgs ca) {
   double acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-  if (tid < S::NT) {
+  if constexpr (SPLIT) {
+    const double gm1i = 1.0 / (pc.gamma - 1.0);
+    bool far = false;
+    if (tid < S::NT) split_sweep_curv<DIM, N, 0, false>(tid, ii, stride, own, sQ, sJ, Ja, sD, gm1i, far, acc);
+    if (far) sFar = 1;
+    __syncthreads();
+    if (sFar) {  // block-uniform: some pair is too far apart for the series
+      if (tid < S::NT) {
+        sQ[DIM + 3][tid] = log(u[0]);
+        sQ[DIM + 4][tid] = log(2.0 * own.hb);
+      }
+      __syncthreads();
+      if (far) {  // only the lanes that flagged a far pair redo their sum
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+        split_sweep_curv<DIM, N, 0, true>(tid, ii, stride, own, sQ, sJ, Ja, sD, gm1i, far, acc);
+      }
+    }
+  } else if (tid < S::NT) {
 #pragma unroll
     for (int l = 0; l < DIM; ++l) {
       const int il = ii[l];
@@ -173,10 +227,18 @@ k_stage_curv(StageParams sp, MeshView mv, PhysConst pc, CurvArgs ca) {
   for (int l = 0; l < DIM; ++l) {
     if (side[l] < 0) continue;  // lanes not on a face in direction l
     const int code = nbl[2 * l + side[l]];
-    if (code == -(1 + DG_BC_OUTFLOW)) continue;  // F* = own flux
     double Fo[NV];
+    if constexpr (SPLIT) {
+      normal_flux<DIM>(u, vel, th.p, Ja[l], Fo);
+      // the split sum's m = i term, -2 D_ii Ft^l(U_i) (D_ii = 0 off the faces)
+      const double cd = -2.0 * sD[ii[l] * (n + 1)];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Fo[v] = sF[l][v][tid < S::NT ? tid : 0];
+      for (int v = 0; v < NV; ++v) acc[v] = fma(cd, Fo[v], acc[v]);
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Fo[v] = sF[l][v][tid < S::NT ? tid : 0];
+    }
+    if (code == -(1 + DG_BC_OUTFLOW)) continue;  // F* = own flux
     double nrm2 = 0.0;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) nrm2 = fma(Ja[l][d], Ja[l][d], nrm2);
@@ -278,7 +340,12 @@ template <int DIM, int N>
 static hipError_t go_curv(const Ctx& c, const StageParams& sp, const CurvArgs& ca, hipStream_t s) {
   using SH = Shape<DIM, N>;
   const int nEB = (c.E + SH::EPB - 1) / SH::EPB;
-  hipLaunchKernelGGL((k_stage_curv<DIM, N>), dim3(nEB * c.B), dim3(SH::BS), 0, s, sp, mesh_view(c), c.pc, ca);
+  if (c.desc.volume == DG_VOLUME_SPLIT)
+    hipLaunchKernelGGL((k_stage_curv<DIM, N, true>), dim3(nEB * c.B), dim3(SH::BS), 0, s, sp, mesh_view(c), c.pc,
+                       ca);
+  else
+    hipLaunchKernelGGL((k_stage_curv<DIM, N, false>), dim3(nEB * c.B), dim3(SH::BS), 0, s, sp, mesh_view(c), c.pc,
+                       ca);
   return hipGetLastError();
 }
 

@@ -2,7 +2,10 @@
 against the oracle's CurvOperator: warped periodic meshes at several degrees
 in 2-D and 3-D, slip walls and supersonic in/outflow on warped meshes, free
 stream and conservation, batched stages, an SSPRK54 step, the warped node
-coordinates, the full 32^3 workload, and the unsupported combinations."""
+coordinates, the full 32^3 workload, and the unsupported combinations; the
+split-form volume integral on the same meshes (rough states that take the
+exact log means and smooth ones that take the series, boundaries, free stream
+and conservation, the full 32^3 workload)."""
 
 import math
 
@@ -27,11 +30,11 @@ def half_turns(dim):
     return [(0, 1)] if dim == 2 else [(0, 1), (1, 2), (0, 2)]
 
 
-def pair(dim, N, nel, lo, hi, warp, bc=None, bc_state=None, batch=1):
+def pair(dim, N, nel, lo, hi, warp, bc=None, bc_state=None, batch=1, volume="standard"):
     from paper_2605_26388_amd import Solver
     m = CurvMesh(dim, N, nel, lo, hi, warp, bc=bc)
-    op = CurvOperator(m, bc_state=bc_state)
-    s = Solver(dim, N, nel, lo, hi, batch=batch, warp=warp, bc=bc, bc_state=bc_state)
+    op = CurvOperator(m, bc_state=bc_state, volume=volume)
+    s = Solver(dim, N, nel, lo, hi, batch=batch, warp=warp, bc=bc, bc_state=bc_state, volume=volume)
     assert s.E == m.base.E
     return op, s
 
@@ -141,3 +144,80 @@ def test_curvilinear_adjoint_rejected():
     with pytest.raises(DGError) as e:
         s.rhs_adjoint(U, s.empty())
     assert e.value.code == DG_ERR_UNSUPPORTED
+
+
+# --- split form --------------------------------------------------------------------
+
+def smooth_state(op, drho=0.02):
+    """A smooth state whose node pairs all stay on the series path of the log
+    means (density and pressure within a few per cent)."""
+    X = op.mesh.X
+    dim = op.dim
+    arg = sum(2 * math.pi * X[d] * (d + 1) for d in range(dim))
+    rho = 1.0 + drho * torch.sin(arg)
+    vel = [0.2 * torch.cos(arg + d) for d in range(dim)]
+    p = 0.9 + drho * torch.cos(arg)
+    return torch.tensor(di.conserved_from_primitive(rho.numpy(), [v.numpy() for v in vel], p.numpy(), G))[None]
+
+
+@pytest.mark.parametrize("dim,N", [(2, 1), (2, 3), (2, 5), (3, 1), (3, 2), (3, 3), (3, 4)])
+@pytest.mark.parametrize("kind", ["rough", "smooth"])
+def test_curvilinear_split_rhs_parity_periodic(dim, N, kind):
+    nel = (7, 5) if dim == 2 else (5, 3, 3)
+    lo, hi = (0.0,) * dim, (1.0, 1.3, 0.9)[:dim]
+    op, s = pair(dim, N, nel, lo, hi, 0.04, volume="split")
+    U = rand_state(op, 30 + N) if kind == "rough" else smooth_state(op)
+    ref, spread = rounding_spread(op.rhs, U, nel, half_turns(dim))
+    got = from_gpu(op, s.rhs(to_gpu(s, U)))
+    err = spread_err(got, ref, spread)
+    print(f"curvilinear split {kind} dim {dim} N {N}: rel err {rel_err(got, ref):.3e}, err/bound {err:.3f}",
+          flush=True)
+    assert err < 1.0
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_curvilinear_split_walls_and_inflow_outflow(dim):
+    nel = (6, 5) if dim == 2 else (4, 3, 3)
+    lo, hi = (0.0,) * dim, (1.0, 1.1, 0.9)[:dim]
+    op, s = pair(dim, 3, nel, lo, hi, 0.03, bc=("wall",) * (2 * dim), volume="split")
+    U = rand_state(op, 41)
+    assert rel_err(from_gpu(op, s.rhs(to_gpu(s, U))), op.rhs(U)) < TOL64
+    ub = di.conserved_from_primitive(np.array([1.0]), [np.array([2.5])] + [np.array([0.2])] * (dim - 1),
+                                     np.array([1.0 / G]), G)[:, 0]
+    bc = ("inflow", "outflow") + ("wall", "wall") + ("periodic", "periodic") * (dim - 2)
+    op, s = pair(dim, 3, nel, lo, hi, 0.03, bc=bc, bc_state=ub, volume="split")
+    U = rand_state(op, 42, vmax=0.3)
+    U[:, 1] = U[:, 1] + 2.0 * U[:, 0]
+    U[:, -1] = U[:, -1] + 0.5 * ((U[:, 1] ** 2 - (U[:, 1] - 2.0 * U[:, 0]) ** 2) / U[:, 0])
+    assert rel_err(from_gpu(op, s.rhs(to_gpu(s, U))), op.rhs(U)) < TOL64
+
+
+def test_curvilinear_split_free_stream_conservation_and_stage():
+    op, s = pair(3, 3, (6, 5, 4), (0, 0, 0), (1.0, 1.0, 1.0), 0.05, volume="split", batch=2)
+    c = s.empty()
+    c[:, 0], c[:, 1], c[:, 2], c[:, 3] = 1.1, 0.33, -0.22, 0.11
+    c[:, 4] = 0.9 / 0.4 + 0.5 * (0.33 ** 2 + 0.22 ** 2 + 0.11 ** 2) / 1.1
+    assert float(s.rhs(c).abs().max()) < 1e-12 * 20.0
+    U = rand_state(op, 5, B=2)
+    dU = s.rhs(to_gpu(s, U))
+    I = s.integrals(dU)[:, :-1]
+    S = s.integrals(dU.abs())[:, :-1]
+    assert np.abs(I / S).max() < 1e-13
+    U0 = rand_state(op, 6, B=2)
+    out = s.empty()
+    s.rk_stage(to_gpu(s, U0), to_gpu(s, U), out, 0.75, 0.25, 0.002)
+    assert rel_err(from_gpu(op, out), rk_stage(op, U0, U, 0.75, 0.25, 0.002)) < TOL64
+
+
+def test_curvilinear_split_full_size_workload():
+    """32^3 warped periodic box, N = 3, split form: dU/dt against the oracle
+    within the measured rounding floor."""
+    p = di.PRESETS["euler3d"]
+    op, s = pair(3, 3, p["nel"], p["lo"], p["hi"], 0.03, volume="split")
+    U = torch.tensor(di.random_euler(op.mesh.coords(), p["lo"], p["hi"]))[None]
+    ref, spread = rounding_spread(op.rhs, U, p["nel"], half_turns(3))
+    got = from_gpu(op, s.rhs(to_gpu(s, U)))
+    err = spread_err(got, ref, spread)
+    print(f"curvilinear split 32^3 rhs: rel err {rel_err(got, ref):.3e}, err/bound {err:.3f}", flush=True)
+    assert err < 1.0
+    assert s.status()["nonphysical"] == 0
