@@ -470,10 +470,10 @@ def bench_curvilinear(steps, warmup):
     from paper_2605_26388_amd import Solver
     p = di.PRESETS["euler3d"]
     out = {}
-    for volume in ("standard", "split"):
-        s = Solver(3, p["N"], p["nel"], p["lo"], p["hi"], warp=0.03, volume=volume)
+    for volume, prec in (("standard", "f64"), ("split", "f64"), ("standard", "f32")):
+        s = Solver(3, p["N"], p["nel"], p["lo"], p["hi"], warp=0.03, volume=volume, precision=prec)
         X = s.node_coords().cpu().numpy()
-        U = torch.tensor(di.random_euler(X, p["lo"], p["hi"]))[None].to(s.device).contiguous()
+        U = torch.tensor(di.random_euler(X, p["lo"], p["hi"]))[None].to(s.device, s.dtype).contiguous()
         dt = s.dt_cfl(U, p["cfl"])
         wall, kern, _ = time_stages(s, U, dt, steps, warmup)
         st = s.status()
@@ -482,14 +482,16 @@ def bench_curvilinear(steps, warmup):
         dof = nodes * s.nv
         byt = WORDS_PER_DOF_STAGE * 8 * dof + 10 * 8 * nodes
         s.close()
-        if volume == "standard":
+        if prec == "f32":
+            out["f32"] = {"kernel_us": kern * 1e6, "value": dof * 3 * steps / wall}
+        elif volume == "standard":
             out.update({"kernel_us": kern * 1e6, "value": dof * 3 * steps / wall, "bytes_per_launch": byt,
                         "roofline": {"bound": "hbm", "achieved": byt / kern / 1e9, "peak": HBM_PEAK_GBS,
                                      "unit": "GB/s", "frac": byt / kern / 1e9 / HBM_PEAK_GBS}})
         else:
             out["split"] = {"kernel_us": kern * 1e6, "value": dof * 3 * steps / wall}
     out["workload"] = ("euler3d warped: 3-D Euler 32^3, N=3, warp 0.03 (per-node metrics), periodic, FP64; "
-                       "split: the same with the split-form volume integral")
+                       "split: the same with the split-form volume integral; f32: FP32 state, standard form")
     return out
 
 

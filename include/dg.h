@@ -179,8 +179,10 @@ typedef struct dg_desc {
    * curl form in 3-D).  bc[2l] / bc[2l+1] is the type of the lo / hi side of
    * direction l (dg_bc; both periodic or neither); bc_state is the conserved
    * state of inflow sides.  Curvilinear meshes (warp != 0 or a non-periodic
-   * side): Euler physics, FP64, standard volume integral, no refined patch, no
-   * adjoint; the mesh must not fold (J > 0 at every node). */
+   * side): Euler physics, both volume integrals (the split form pairs the
+   * two-point flux with the average of the two nodes' Ja^l), FP64 or FP32
+   * state (the FP32 form computes in double), no refined patch, no adjoint;
+   * the mesh must not fold (J > 0 at every node). */
   double warp;
   int32_t bc[6];
   double bc_state[5];

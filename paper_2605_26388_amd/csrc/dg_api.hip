@@ -610,7 +610,6 @@ int dg_create(const dg_desc* desc, dg_ctx** out) {
   if (curv) {
     if (d.physics != DG_EULER) return fail(DG_ERR_UNSUPPORTED, "curvilinear meshes and boundaries: Euler physics only");
     if (patch) return fail(DG_ERR_UNSUPPORTED, "curvilinear meshes and boundaries: no refined patch");
-    if (d.precision != DG_F64) return fail(DG_ERR_UNSUPPORTED, "curvilinear meshes and boundaries: FP64 only");
     bool inflow = false;
     for (int q = 0; q < 2 * d.dim; ++q) inflow = inflow || d.bc[q] == DG_BC_INFLOW;
     if (inflow) {

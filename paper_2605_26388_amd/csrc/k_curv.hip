@@ -28,6 +28,8 @@
 // kernel, with the same exact redo for widely separated pairs); its m = i term
 // -2 D_ii Ft^l(U_i) is added on the face lanes, whose own flux Ft^l is then
 // evaluated in registers; the surface term is unchanged.
+// FP32 form (T = float): the state is read and written in float; all
+// arithmetic, the metrics and the LDS tiles stay in double.
 #include <type_traits>
 
 #include "dg_device.hpp"
@@ -53,7 +55,7 @@ __device__ __forceinline__ void normal_flux(const double (&U)[DIM + 2], const do
   F[DIM + 1] = (U[DIM + 1] + p) * vn;
 }
 
-template <int DIM, int N, bool SPLIT>
+template <int DIM, int N, bool SPLIT, typename T>
 __global__ void __launch_bounds__((Shape<DIM, N>::BS)) __attribute__((amdgpu_waves_per_eu(3)))
 k_stage_curv(StageParams sp, MeshView mv, PhysConst pc, CurvArgs ca) {
   using S = Shape<DIM, N>;
@@ -97,14 +99,14 @@ k_stage_curv(StageParams sp, MeshView mv, PhysConst pc, CurvArgs ca) {
   const int stride[3] = {1, n, n * n};
 
   const size_t plane = (size_t)E * NP;
-  const size_t abytes = (size_t)NV * plane * sizeof(double);
-  const unsigned pstride = (unsigned)(plane * sizeof(double));
-  const rsrc_t rU = make_rsrc(static_cast<const double*>(sp.Uk) + (size_t)b * NV * plane, abytes);
+  const size_t abytes = (size_t)NV * plane * sizeof(T);
+  const unsigned pstride = (unsigned)(plane * sizeof(T));
+  const rsrc_t rU = make_rsrc(static_cast<const T*>(sp.Uk) + (size_t)b * NV * plane, abytes);
   const unsigned off = (unsigned)(ec * NP + node);
 
   double u[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) u[v] = Buf<double>::load(rU, off, v * pstride);
+  for (int v = 0; v < NV; ++v) u[v] = Buf<T>::load(rU, off, v * pstride);
   // metrics of the own node (shared by all batch members)
   const size_t at = (size_t)ec * NP + node;
   const double jinv = ca.met[plane + at];
@@ -214,7 +216,7 @@ k_stage_curv(StageParams sp, MeshView mv, PhysConst pc, CurvArgs ca) {
       const int shift = side[l] == 1 ? -N : N;
       const unsigned noff = (unsigned)(ne * NP + node + shift * stride[l]);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) un[l][v] = Buf<double>::load(rU, noff, v * pstride);
+      for (int v = 0; v < NV; ++v) un[l][v] = Buf<T>::load(rU, noff, v * pstride);
     } else {
 #pragma unroll
       for (int v = 0; v < NV; ++v) un[l][v] = u[v];
@@ -300,16 +302,16 @@ k_stage_curv(StageParams sp, MeshView mv, PhysConst pc, CurvArgs ca) {
   if (active) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] *= jinv;
-    const rsrc_t ro = make_rsrc(static_cast<double*>(sp.out) + (size_t)b * NV * plane, abytes);
+    const rsrc_t ro = make_rsrc(static_cast<T*>(sp.out) + (size_t)b * NV * plane, abytes);
     if (sp.mode == 0) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Buf<double>::store(ro, off, acc[v], v * pstride);
+      for (int v = 0; v < NV; ++v) Buf<T>::store(ro, off, acc[v], v * pstride);
     } else {
       double u0[NV];
       if (use_u0) {
-        const rsrc_t r0 = make_rsrc(static_cast<const double*>(sp.U0) + (size_t)b * NV * plane, abytes);
+        const rsrc_t r0 = make_rsrc(static_cast<const T*>(sp.U0) + (size_t)b * NV * plane, abytes);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) u0[v] = Buf<double>::load(r0, off, v * pstride);
+        for (int v = 0; v < NV; ++v) u0[v] = Buf<T>::load(r0, off, v * pstride);
       }
       double r[NV];
 #pragma unroll
@@ -320,32 +322,40 @@ k_stage_curv(StageParams sp, MeshView mv, PhysConst pc, CurvArgs ca) {
       if (sp.rho_min > 0.0 || sp.p_min > 0.0)
         positivity_floor(r, sp.rho_min, sp.p_min, 1.0 / (pc.gamma - 1.0), mv.counters);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Buf<double>::store(ro, off, r[v], v * pstride);
+      for (int v = 0; v < NV; ++v) Buf<T>::store(ro, off, r[v], v * pstride);
       if (sp.mode == 2) {  // second combination of the same L(Uk), no floor
-        const rsrc_t r2 = make_rsrc(static_cast<double*>(sp.out2) + (size_t)b * NV * plane, abytes);
+        const rsrc_t r2 = make_rsrc(static_cast<T*>(sp.out2) + (size_t)b * NV * plane, abytes);
         const bool use_v = sp.a2 != 0.0;
-        const rsrc_t rv = make_rsrc(static_cast<const double*>(use_v ? sp.V : sp.Uk) + (size_t)b * NV * plane, abytes);
+        const rsrc_t rv = make_rsrc(static_cast<const T*>(use_v ? sp.V : sp.Uk) + (size_t)b * NV * plane, abytes);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           double w = fma(sp.c2, acc[v], sp.b2 * u[v]);
-          if (use_v) w = fma(sp.a2, Buf<double>::load(rv, off, v * pstride), w);
-          Buf<double>::store(r2, off, w, v * pstride);
+          if (use_v) w = fma(sp.a2, Buf<T>::load(rv, off, v * pstride), w);
+          Buf<T>::store(r2, off, w, v * pstride);
         }
       }
     }
   }
 }
 
-template <int DIM, int N>
-static hipError_t go_curv(const Ctx& c, const StageParams& sp, const CurvArgs& ca, hipStream_t s) {
+template <int DIM, int N, typename T>
+static void go_curv_t(const Ctx& c, const StageParams& sp, const CurvArgs& ca, hipStream_t s) {
   using SH = Shape<DIM, N>;
   const int nEB = (c.E + SH::EPB - 1) / SH::EPB;
   if (c.desc.volume == DG_VOLUME_SPLIT)
-    hipLaunchKernelGGL((k_stage_curv<DIM, N, true>), dim3(nEB * c.B), dim3(SH::BS), 0, s, sp, mesh_view(c), c.pc,
-                       ca);
+    hipLaunchKernelGGL((k_stage_curv<DIM, N, true, T>), dim3(nEB * c.B), dim3(SH::BS), 0, s, sp, mesh_view(c),
+                       c.pc, ca);
   else
-    hipLaunchKernelGGL((k_stage_curv<DIM, N, false>), dim3(nEB * c.B), dim3(SH::BS), 0, s, sp, mesh_view(c), c.pc,
-                       ca);
+    hipLaunchKernelGGL((k_stage_curv<DIM, N, false, T>), dim3(nEB * c.B), dim3(SH::BS), 0, s, sp, mesh_view(c),
+                       c.pc, ca);
+}
+
+template <int DIM, int N>
+static hipError_t go_curv(const Ctx& c, const StageParams& sp, const CurvArgs& ca, hipStream_t s) {
+  if (c.desc.precision == DG_F32)
+    go_curv_t<DIM, N, float>(c, sp, ca, s);
+  else
+    go_curv_t<DIM, N, double>(c, sp, ca, s);
   return hipGetLastError();
 }
 
@@ -364,7 +374,7 @@ static hipError_t curv_n(const Ctx& c, const StageParams& sp, const CurvArgs& ca
 }
 
 hipError_t launch_curv(const Ctx& c, const StageParams& sp, hipStream_t s) {
-  if (c.desc.precision != DG_F64 || c.desc.physics != DG_EULER) return hipErrorInvalidValue;
+  if (c.desc.physics != DG_EULER) return hipErrorInvalidValue;
   CurvArgs ca;
   ca.met = c.d_met;
   for (int v = 0; v < 5; ++v) ca.ub[v] = c.desc.bc_state[v];

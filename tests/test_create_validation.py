@@ -87,7 +87,6 @@ def create(d):
     (dict(bc=(1, 0, 0, 0, 0, 0)), _abi.DG_ERR_ARG, "periodic"),
     (dict(bc=(7, 7, 0, 0, 0, 0)), _abi.DG_ERR_ARG, "dg_bc"),
     (dict(warp=0.05, physics=_abi.DG_NAVIER_STOKES), _abi.DG_ERR_UNSUPPORTED, "Euler"),
-    (dict(warp=0.05, precision=_abi.DG_F32), _abi.DG_ERR_UNSUPPORTED, "FP64"),
     (dict(dim=2, nel=(8, 8), patch=((2, 2), (4, 4)), bc=(1, 1, 0, 0)), _abi.DG_ERR_UNSUPPORTED, "patch"),
     (dict(bc=(2, 3, 0, 0, 0, 0), bc_state=(1.0, 0.0, 0.0, 0.0, -1.0)), _abi.DG_ERR_ARG, "bc_state"),
 ])
@@ -119,7 +118,8 @@ def test_null_arguments():
                                 dict(rho_floor=1e-6, p_floor=5e-7),
                                 dict(physics=_abi.DG_REACTING_2T, dim=2, nel=(8, 8), mech="air5", vib="air5"),
                                 dict(warp=0.05, bc=(1, 1, 2, 3, 0, 0), bc_state=(1.0, 0.0, 2.0, 0.0, 5.0)),
-                                dict(warp=0.05, volume=_abi.DG_VOLUME_SPLIT)])
+                                dict(warp=0.05, volume=_abi.DG_VOLUME_SPLIT),
+                                dict(warp=0.05, precision=_abi.DG_F32)])
 def test_valid_descriptor_passes_the_checks(kw):
     rc, err = create(desc(**kw))
     # no device here: the only failure left is the device query itself

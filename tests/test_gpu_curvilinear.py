@@ -5,7 +5,8 @@ stream and conservation, batched stages, an SSPRK54 step, the warped node
 coordinates, the full 32^3 workload, and the unsupported combinations; the
 split-form volume integral on the same meshes (rough states that take the
 exact log means and smooth ones that take the series, boundaries, free stream
-and conservation, the full 32^3 workload)."""
+and conservation, the full 32^3 workload); the FP32 form (float state, double
+arithmetic) against the FP32 accuracy statement."""
 
 import math
 
@@ -30,11 +31,12 @@ def half_turns(dim):
     return [(0, 1)] if dim == 2 else [(0, 1), (1, 2), (0, 2)]
 
 
-def pair(dim, N, nel, lo, hi, warp, bc=None, bc_state=None, batch=1, volume="standard"):
+def pair(dim, N, nel, lo, hi, warp, bc=None, bc_state=None, batch=1, volume="standard", precision="f64"):
     from paper_2605_26388_amd import Solver
     m = CurvMesh(dim, N, nel, lo, hi, warp, bc=bc)
     op = CurvOperator(m, bc_state=bc_state, volume=volume)
-    s = Solver(dim, N, nel, lo, hi, batch=batch, warp=warp, bc=bc, bc_state=bc_state, volume=volume)
+    s = Solver(dim, N, nel, lo, hi, batch=batch, warp=warp, bc=bc, bc_state=bc_state, volume=volume,
+               precision=precision)
     assert s.E == m.base.E
     return op, s
 
@@ -220,4 +222,39 @@ def test_curvilinear_split_full_size_workload():
     err = spread_err(got, ref, spread)
     print(f"curvilinear split 32^3 rhs: rel err {rel_err(got, ref):.3e}, err/bound {err:.3f}", flush=True)
     assert err < 1.0
+    assert s.status()["nonphysical"] == 0
+
+
+# --- FP32 form ----------------------------------------------------------------------
+
+@pytest.mark.parametrize("volume", ["standard", "split"])
+@pytest.mark.parametrize("case", ["periodic 3-D", "walls 2-D", "32^3"])
+def test_curvilinear_fp32_statement(volume, case):
+    """Float state, double arithmetic: the RHS at the float-rounded state
+    against the oracle there (the kernel's own error: the float rounding of
+    its output, asserted at the FP32 target 1e-5) and end to end against the
+    oracle at the double state (at most the quantisation floor + 1e-5); a
+    stage at the float-rounded states to the output rounding."""
+    if case == "periodic 3-D":
+        op, s = pair(3, 3, (5, 3, 3), (0, 0, 0), (1.0, 1.3, 0.9), 0.04, volume=volume, precision="f32")
+        U = smooth_state(op)
+    elif case == "walls 2-D":
+        op, s = pair(2, 4, (6, 5), (0, 0), (1.0, 1.1), 0.03, bc=("wall",) * 4, volume=volume, precision="f32")
+        U = smooth_state(op)
+    else:
+        p = di.PRESETS["euler3d"]
+        op, s = pair(3, 3, p["nel"], p["lo"], p["hi"], 0.03, volume=volume, precision="f32")
+        U = torch.tensor(di.random_euler(op.mesh.coords(), p["lo"], p["hi"]))[None]
+    Uq = U.float().double()
+    got = from_gpu(op, s.rhs(to_gpu(s, Uq)))
+    ref_q, ref = op.rhs(Uq), op.rhs(U)
+    e_arith, e_quant, e_total = rel_err(got, ref_q), rel_err(ref_q, ref), rel_err(got, ref)
+    print(f"FP32 curvilinear {volume} {case}: arithmetic {e_arith:.3e}, quantisation floor {e_quant:.3e}, "
+          f"end to end {e_total:.3e}", flush=True)
+    assert e_arith < 1e-5
+    assert e_total <= e_quant + 1e-5
+    U0q = (1.01 * U).float().double()
+    out = s.empty()
+    s.rk_stage(to_gpu(s, U0q), to_gpu(s, Uq), out, 0.75, 0.25, 0.002)
+    assert rel_err(from_gpu(op, out), rk_stage(op, U0q, Uq, 0.75, 0.25, 0.002)) < 1e-7
     assert s.status()["nonphysical"] == 0
