@@ -39,6 +39,17 @@ conservation and entropy conservation rest on the discrete GCL above); the
 surface term is unchanged (F* - Ft^l(U_i) at face nodes).  surface="ec" puts
 the two-point flux itself at the interfaces, F#(U_L, U_R) . n with each side's
 own n, for the entropy check.
+BR1 viscous terms (viscous=dict(mu, prandtl, gamma); periodic meshes): the
+gradient of W = (rho, u, v, w, T) by the strong-form operator of the
+hyperbolic pipeline applied to the flux W e_d (reading of Parabolic Terms,
+step 1: same structure as the hyperbolic surface pipeline, then rescaled by
+1/J),
+    J S_d = sum_l [ sum_m D_im (Ja^l_d W)_m + (+-1/w_end)(W^ - W_i) Ja^l_d,i ],
+W^ = (W^- + W^+)/2 on the face (eq. br1_avg); the contravariant viscous
+fluxes Fv~^l = Ja^l . F_v(U, S) (eq. tau, q = -k grad T), their strong-form
+divergence and the central interface flux {{Fv~^l}} (eq. br1_flux), the
+average of the two sides' own contravariant fluxes at the shared face node
+(the two Ja^l agree there to rounding), added with a + sign.
 Boundary faces (box sides that are not periodic), per type:
     wall     slip wall: ghost state with the normal velocity reversed,
              U_g = (rho, m - 2 (m . n^) n^, E), in the Rusanov flux (its mass
@@ -54,7 +65,7 @@ import torch
 
 from .dgsem import dsweep, node_axis, trace
 from .mesh import cartesian_mesh
-from .physics import Euler
+from .physics import Euler, viscous_flux
 from .refelem import gll
 from .split import ranocha_flux_n as split_ranocha_n
 
@@ -147,14 +158,61 @@ class CurvOperator:
     """L(U) for the Euler equations on a CurvMesh (strong form); bc_state is
     the prescribed conserved state of inflow sides."""
 
-    def __init__(self, mesh, gamma=1.4, bc_state=None, volume="standard", surface="rusanov"):
+    def __init__(self, mesh, gamma=1.4, bc_state=None, volume="standard", surface="rusanov", viscous=None):
         if volume not in ("standard", "split") or surface not in ("rusanov", "ec"):
             raise ValueError((volume, surface))
+        if viscous is not None and any(b != "periodic" for b in mesh.bc):
+            raise ValueError("viscous terms on curvilinear meshes: periodic sides only")
         self.mesh = mesh
         self.phys = Euler(mesh.dim, gamma)
         self.dim, self.N, self.n = mesh.dim, mesh.N, mesh.n
         self.bc_state = None if bc_state is None else torch.tensor(bc_state, dtype=torch.float64)
         self.volume, self.surface = volume, surface
+        self.viscous = viscous  # dict(mu, prandtl, gamma) or None
+
+    def br1_gradient(self, W):
+        """S[q][d] = d W_q / d x_d (W: (B, nq, E, nodes)), the strong-form
+        lifted gradient with per-node metrics."""
+        m, dim, N = self.mesh, self.dim, self.N
+        winv = 1.0 / float(m.w[0])
+        Sd = []
+        for d in range(dim):
+            G = torch.zeros_like(W)
+            for l in range(dim):
+                ax = node_axis(dim, l)
+                Jd = m.Ja[l][d][None, None]
+                G = G + dsweep(Jd * W, m.D, dim, l)
+                Lr, Rr = (torch.as_tensor(a) for a in m.pairs[l])
+                WL = trace(W[:, :, Lr], dim, l, N)
+                WR = trace(W[:, :, Rr], dim, l, 0)
+                What = 0.5 * (WL + WR)
+                nL = trace(Jd[:, :, Lr], dim, l, N)
+                nR = trace(Jd[:, :, Rr], dim, l, 0)
+                G[:, :, Lr] = _add_face(G[:, :, Lr], winv * (What - WL) * nL, dim, ax, N)
+                G[:, :, Rr] = _add_face(G[:, :, Rr], -winv * (What - WR) * nR, dim, ax, 0)
+            Sd.append(G / m.J[None, None])
+        return [[Sd[d][:, q] for d in range(dim)] for q in range(W.shape[1])]
+
+    def rhs_viscous(self, U):
+        """(1/J) [sum_l D Fv~^l + lift of ({{Fv~^l}} - Fv~^l)] with Fv~^l = Ja^l . F_v."""
+        m, ph, dim, N, vis = self.mesh, self.phys, self.dim, self.N, self.viscous
+        P = ph.prims(U)
+        W = torch.stack([P["rho"]] + P["u"] + [P["p"] / P["rho"]], dim=1)
+        S = self.br1_gradient(W)
+        Fv = [viscous_flux(dim, P, S, d, vis["mu"], vis["gamma"], vis["prandtl"]) for d in range(dim)]
+        winv = 1.0 / float(m.w[0])
+        dU = torch.zeros_like(U)
+        for l in range(dim):
+            ax = node_axis(dim, l)
+            Ft = self._ft(Fv, m.Ja[l])
+            dU = dU + dsweep(Ft, m.D, dim, l)
+            Lr, Rr = (torch.as_tensor(a) for a in m.pairs[l])
+            FL = trace(Ft[:, :, Lr], dim, l, N)
+            FR = trace(Ft[:, :, Rr], dim, l, 0)
+            Fs = 0.5 * (FL + FR)
+            dU[:, :, Lr] = _add_face(dU[:, :, Lr], winv * (Fs - FL), dim, ax, N)
+            dU[:, :, Rr] = _add_face(dU[:, :, Rr], -winv * (Fs - FR), dim, ax, 0)
+        return dU / m.J[None, None]
 
     def split_volume(self, U):
         """-sum_l sum_m 2 D_im F#(U_i, U_m) . (Ja^l_i + Ja^l_m) / 2 (times J)."""
@@ -251,7 +309,10 @@ class CurvOperator:
                 Fs = self._boundary_flux(m.bc[2 * l + 1], Ui, n, own_is_left=True)
                 Fo = trace(Ft[l][:, :, hi_el], dim, l, m.N)
                 dU[:, :, hi_el] = _add_face(dU[:, :, hi_el], -winv * (Fs - Fo), dim, ax, m.N)
-        return dU / m.J[None, None]
+        dU = dU / m.J[None, None]
+        if self.viscous is not None:
+            dU = dU + self.rhs_viscous(U)
+        return dU
 
     def lam_max(self, U):
         P = self.phys.prims(U)
