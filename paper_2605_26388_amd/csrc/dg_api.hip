@@ -608,7 +608,16 @@ int dg_create(const dg_desc* desc, dg_ctx** out) {
     if (a != DG_BC_PERIODIC) curv = true;
   }
   if (curv) {
-    if (d.physics != DG_EULER) return fail(DG_ERR_UNSUPPORTED, "curvilinear meshes and boundaries: Euler physics only");
+    bool periodic = true;
+    for (int q = 0; q < 2 * d.dim; ++q) periodic = periodic && d.bc[q] == DG_BC_PERIODIC;
+    if (d.physics == DG_NAVIER_STOKES) {
+      if (!periodic)
+        return fail(DG_ERR_UNSUPPORTED, "curvilinear Navier-Stokes: periodic sides only (no viscous boundary fluxes)");
+      if (d.volume != DG_VOLUME_STANDARD)
+        return fail(DG_ERR_UNSUPPORTED, "curvilinear Navier-Stokes: standard volume integral only");
+    } else if (d.physics != DG_EULER) {
+      return fail(DG_ERR_UNSUPPORTED, "curvilinear meshes and boundaries: Euler or Navier-Stokes physics only");
+    }
     if (patch) return fail(DG_ERR_UNSUPPORTED, "curvilinear meshes and boundaries: no refined patch");
     bool inflow = false;
     for (int q = 0; q < 2 * d.dim; ++q) inflow = inflow || d.bc[q] == DG_BC_INFLOW;

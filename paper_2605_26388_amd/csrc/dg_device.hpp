@@ -127,6 +127,19 @@ template <> struct Buf<float> {
   }
 };
 
+// n . F(U) for the Euler flux: (rho v_n, m v_n + p n, (E + p) v_n), v_n = v . n
+template <int DIM>
+__device__ __forceinline__ void normal_flux(const double (&U)[DIM + 2], const double (&vel)[DIM], double p,
+                                            const double (&n)[DIM], double (&F)[DIM + 2]) {
+  double vn = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) vn = fma(vel[d], n[d], vn);
+  F[0] = U[0] * vn;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) F[1 + d] = fma(U[1 + d], vn, p * n[d]);
+  F[DIM + 1] = (U[DIM + 1] + p) * vn;
+}
+
 // Make a value the compiler cannot prove uniform a scalar (only valid when it
 // is uniform across the wave).
 __device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }

@@ -26,6 +26,16 @@
 // -2 (2/h_l) sum_m D_im F#_l(U_i, U_m) of the inviscid stage kernel (its m = i
 // term added on the face lanes with the own physical flux), and the surfaces
 // are unchanged.
+//
+// Curvilinear elements (CURV; periodic warped meshes, standard volume
+// integral): per-node metrics 1/J and Ja^l.  The gradient is the strong-form
+// operator with the metrics inside the sweep, J S_d = sum_l [sum_m D_im (Ja^l_d
+// W)_m + (+-1/w_end) (W^ - W_i) Ja^l_d,i], staged direction by direction
+// (twelve products Ja^l_d W_q per node); the face buffer holds the
+// contravariant viscous flux Ja^l . F_v of the own face node; pass 2 stages
+// G^l = Ja^l . (F_inv - F_v), takes the Rusanov flux along the own node's
+// Ja^l (as the curvilinear Euler stage) and the central viscous flux of the
+// two buffered contravariant fluxes, and scales by 1/J.
 #include <type_traits>
 
 #include "dg_device.hpp"
@@ -70,15 +80,16 @@ __device__ __forceinline__ void visc_flux(const double (&W)[4], const double (&S
   Fv[3] = e;
 }
 
-template <int N, typename T, int PASS, bool SPLIT = false>
+template <int N, typename T, int PASS, bool SPLIT = false, bool CURV = false>
 __global__ void __launch_bounds__((Shape<3, N>::BS))
-k_ns(StageParams sp, MeshView mv, PhysConst pc, T* face) {
+k_ns(StageParams sp, MeshView mv, PhysConst pc, T* face, const double* met) {
   using S = Shape<3, N>;
   constexpr int n = S::n, NP = S::NP, NF = S::NF, EPB = S::EPB, NV = 5;
   using PHYS = EulerPhys<3>;
   constexpr bool SPL = SPLIT && PASS == 2;
+  static_assert(!(SPLIT && CURV), "curvilinear Navier-Stokes: standard volume integral");
 
-  __shared__ double sW[4][EPB * NP];
+  __shared__ double sW[CURV ? 12 : 4][EPB * NP];  // W (curvilinear: Ja^l_d W_q of one direction l)
   __shared__ double sF[PASS == 2 ? 3 : 1][NV][PASS == 2 ? EPB * NP : 1];
   __shared__ double sD[n * n];
   __shared__ double sQ[SPL ? 8 : 1][SPL ? EPB * NP : 1];  // split form: rho/2, v/2, p, rho/(2p), ln rho, ln(rho/p)
@@ -144,10 +155,20 @@ k_ns(StageParams sp, MeshView mv, PhysConst pc, T* face) {
   const double gm1 = pc.gamma - 1.0;
   const double mu = pc.mu;
   const double kc = pc.gamma * pc.mu / (pc.prandtl * gm1);
+  // curvilinear: the node's 1/J and Ja^l_d (shared by all batch members)
+  double jinv = 0.0, Ja[3][3] = {};
+  if constexpr (CURV) {
+    const size_t at = (size_t)ec * NP + node;
+    jinv = met[plane + at];
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) Ja[l][d] = met[(2 + l * 3 + d) * plane + at];
+  }
   double W[4];
   prim_w(u, gm1, W);
   if (tid < n * n) sD[tid] = dval;
-  if (tid < S::NT) {
+  if (!CURV && tid < S::NT) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) sW[q][tid] = W[q];
   }
@@ -159,7 +180,51 @@ k_ns(StageParams sp, MeshView mv, PhysConst pc, T* face) {
   for (int l = 0; l < 3; ++l)
 #pragma unroll
     for (int q = 0; q < 4; ++q) Sg[l][q] = 0.0;
-  if (tid < S::NT) {
+  if constexpr (CURV) {
+    // J S_d = sum_l [D (Ja^l_d W) + lift_l((W^ - W) Ja^l_d)], one direction at a time
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      if (tid < S::NT) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) sW[d * 4 + q][tid] = Ja[l][d] * W[q];
+      }
+      __syncthreads();
+      if (tid < S::NT) {
+        const int il = ii[l], st = stride[l];
+        const int base = tid - il * st;
+        double dr[n];
+#pragma unroll
+        for (int m = 0; m < n; ++m) dr[m] = sD[il * n + m];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            double s = 0.0;
+#pragma unroll
+            for (int m = 0; m < n; ++m) s = fma(dr[m], sW[d * 4 + q][base + m * st], s);
+            Sg[d][q] += s;
+          }
+        if (nbe[l] >= 0) {
+          double Wn[4];
+          prim_w(un[l], gm1, Wn);
+          const double c = (side[l] ? 0.5 : -0.5) * winv;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            const double cd = c * Ja[l][d];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Sg[d][q] = fma(cd, Wn[q] - W[q], Sg[d][q]);
+          }
+        }
+      }
+      __syncthreads();  // the next direction overwrites the staged products
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Sg[d][q] *= jinv;
+  } else if (tid < S::NT) {
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
       const int il = ii[l], st = stride[l];
@@ -190,11 +255,21 @@ k_ns(StageParams sp, MeshView mv, PhysConst pc, T* face) {
   if constexpr (PASS == 1) {
     // normal viscous flux at the element's own face nodes -> face buffer
     if (active) {
+      double Fa[CURV ? 3 : 1][4];  // curvilinear: F_v along every physical direction
+      if constexpr (CURV) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) visc_flux(W, Sg, d, mu, kc, Fa[d]);
+      }
 #pragma unroll
       for (int l = 0; l < 3; ++l) {
         if (side[l] < 0) continue;
         double Fv[4];
-        visc_flux(W, Sg, l, mu, kc, Fv);
+        if constexpr (CURV) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) Fv[c] = Ja[l][0] * Fa[0][c] + Ja[l][1] * Fa[1][c] + Ja[l][2] * Fa[2][c];
+        } else {
+          visc_flux(W, Sg, l, mu, kc, Fv);
+        }
         const int f = 2 * l + side[l];
         T* dst = face + ((((size_t)b * E + e) * 6 + f) * NF + face_node<n>(ii, l)) * 4;
 #pragma unroll
@@ -212,7 +287,20 @@ k_ns(StageParams sp, MeshView mv, PhysConst pc, T* face) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) vel[d] = u[1 + d] * th.ri;
     SplitNode<3> own;
-    if (tid < S::NT) {
+    if (CURV && tid < S::NT) {
+      double Fa[3][4];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) visc_flux(W, Sg, d, mu, kc, Fa[d]);
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        double F[NV];
+        normal_flux<3>(u, vel, th.p, Ja[l], F);
+        sF[l][0][tid] = F[0];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          sF[l][1 + q][tid] = F[1 + q] - (Ja[l][0] * Fa[0][q] + Ja[l][1] * Fa[1][q] + Ja[l][2] * Fa[2][q]);
+      }
+    } else if (tid < S::NT) {
 #pragma unroll
       for (int l = 0; l < 3; ++l) {
         double F[NV], Fv[4];
@@ -285,7 +373,7 @@ k_ns(StageParams sp, MeshView mv, PhysConst pc, T* face) {
         const int base = tid - il * st;
         double dr[n];
 #pragma unroll
-        for (int m = 0; m < n; ++m) dr[m] = sD[il * n + m] * (-g[l]);
+        for (int m = 0; m < n; ++m) dr[m] = CURV ? -sD[il * n + m] : sD[il * n + m] * (-g[l]);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           double s = 0.0;
@@ -321,18 +409,40 @@ k_ns(StageParams sp, MeshView mv, PhysConst pc, T* face) {
         // (F_nb - F_own) - s lam (U_nb - U_own), s = +1 on the +xi_l face;
         // the central viscous flux likewise, 2 ({{F_v}} - F_v,own) = F_v,nb - F_v,own.
         double Fo[NV], Fn[NV], Dv[NV];
-        PHYS::flux(u, vel[l], th.p, l, Fo);
         Thermo tn;
         PHYS::thermo(un[l], tn, pc);
-        const double vn = un[l][1 + l] * tn.ri;
-        PHYS::flux(un[l], vn, tn.p, l, Fn);
-        const double co = fabs(vel[l]) + aown;
-        const double cn = fabs(vn) + sound<PHYS>(tn);
-        const double lam = co >= cn ? co : cn;
-        const double hs = side[l] ? lam : -lam;
+        double hs;
+        if constexpr (CURV) {  // Rusanov along the own node's Ja^l (|Ja^l| times the unit-normal flux)
+          double vnv[3];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) vnv[d] = un[l][1 + d] * tn.ri;
+          normal_flux<3>(u, vel, th.p, Ja[l], Fo);
+          normal_flux<3>(un[l], vnv, tn.p, Ja[l], Fn);
+          double nrm2 = 0.0, vo = 0.0, vg = 0.0;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            nrm2 = fma(Ja[l][d], Ja[l][d], nrm2);
+            vo = fma(vel[d], Ja[l][d], vo);
+            vg = fma(vnv[d], Ja[l][d], vg);
+          }
+          const double nmag = fsqrt(nrm2);
+          const double nmi = frcp(nmag);
+          const double co = fabs(vo) * nmi + aown;
+          const double cn = fabs(vg) * nmi + sound<PHYS>(tn);
+          const double lam = co >= cn ? co : cn;
+          hs = (side[l] ? lam : -lam) * nmag;
+        } else {
+          PHYS::flux(u, vel[l], th.p, l, Fo);
+          const double vn = un[l][1 + l] * tn.ri;
+          PHYS::flux(un[l], vn, tn.p, l, Fn);
+          const double co = fabs(vel[l]) + aown;
+          const double cn = fabs(vn) + sound<PHYS>(tn);
+          const double lam = co >= cn ? co : cn;
+          hs = side[l] ? lam : -lam;
+        }
 #pragma unroll
         for (int v = 0; v < NV; ++v) Dv[v] = fma(-hs, un[l][v] - u[v], Fn[v] - Fo[v]);
-        const double sc = (side[l] ? -g[l] : g[l]) * (0.5 * winv);
+        const double sc = (side[l] ? -1.0 : 1.0) * (CURV ? 1.0 : g[l]) * (0.5 * winv);
         acc[0] = fma(sc, Dv[0], acc[0]);
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[1 + c] = fma(sc, Dv[1 + c] - (fvn_l[c] - fvo_l[c]), acc[1 + c]);
@@ -343,6 +453,10 @@ k_ns(StageParams sp, MeshView mv, PhysConst pc, T* face) {
           for (int v = 0; v < NV; ++v) acc[v] = fma(cd, Fo[v], acc[v]);
         }
       }
+    }
+    if constexpr (CURV) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[v] *= jinv;
     }
     if (active) {
       T* outb = static_cast<T*>(sp.out) + (size_t)b * NV * plane;
@@ -385,13 +499,21 @@ static hipError_t ns_go(const Ctx& c, const StageParams& sp, hipStream_t s) {
   const int nEB = (c.E + SH::EPB - 1) / SH::EPB;
   const int nblk = nEB * c.B;
   T* face = static_cast<T*>(c.d_face);
-  hipLaunchKernelGGL((k_ns<N, T, 1>), dim3(nblk), dim3(SH::BS), 0, s, sp, mesh_view(c), c.pc, face);
+  const MeshView mv = mesh_view(c);
+  if (c.curv) {
+    hipLaunchKernelGGL((k_ns<N, T, 1, false, true>), dim3(nblk), dim3(SH::BS), 0, s, sp, mv, c.pc, face, c.d_met);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_ns<N, T, 2, false, true>), dim3(nblk), dim3(SH::BS), 0, s, sp, mv, c.pc, face, c.d_met);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL((k_ns<N, T, 1>), dim3(nblk), dim3(SH::BS), 0, s, sp, mv, c.pc, face, nullptr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (c.desc.volume == DG_VOLUME_SPLIT)
-    hipLaunchKernelGGL((k_ns<N, T, 2, true>), dim3(nblk), dim3(SH::BS), 0, s, sp, mesh_view(c), c.pc, face);
+    hipLaunchKernelGGL((k_ns<N, T, 2, true>), dim3(nblk), dim3(SH::BS), 0, s, sp, mv, c.pc, face, nullptr);
   else
-    hipLaunchKernelGGL((k_ns<N, T, 2>), dim3(nblk), dim3(SH::BS), 0, s, sp, mesh_view(c), c.pc, face);
+    hipLaunchKernelGGL((k_ns<N, T, 2>), dim3(nblk), dim3(SH::BS), 0, s, sp, mv, c.pc, face, nullptr);
   return hipGetLastError();
 }
 

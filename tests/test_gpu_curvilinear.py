@@ -6,7 +6,10 @@ coordinates, the full 32^3 workload, and the unsupported combinations; the
 split-form volume integral on the same meshes (rough states that take the
 exact log means and smooth ones that take the series, boundaries, free stream
 and conservation, the full 32^3 workload); the FP32 form (float state, double
-arithmetic) against the FP32 accuracy statement."""
+arithmetic) against the FP32 accuracy statement; Navier-Stokes (BR1 with
+per-node metrics) on warped periodic boxes: rough states at N = 2..4, the
+Taylor-Green state on a warped box, free stream, conservation, stages and an
+SSPRK54 step, FP32."""
 
 import math
 
@@ -31,12 +34,15 @@ def half_turns(dim):
     return [(0, 1)] if dim == 2 else [(0, 1), (1, 2), (0, 2)]
 
 
-def pair(dim, N, nel, lo, hi, warp, bc=None, bc_state=None, batch=1, volume="standard", precision="f64"):
+def pair(dim, N, nel, lo, hi, warp, bc=None, bc_state=None, batch=1, volume="standard", precision="f64",
+         mu=None, prandtl=0.72):
     from paper_2605_26388_amd import Solver
     m = CurvMesh(dim, N, nel, lo, hi, warp, bc=bc)
-    op = CurvOperator(m, bc_state=bc_state, volume=volume)
+    vis = None if mu is None else dict(mu=mu, prandtl=prandtl, gamma=G)
+    op = CurvOperator(m, bc_state=bc_state, volume=volume, viscous=vis)
+    kw = {} if mu is None else dict(physics="navier_stokes", mu=mu, prandtl=prandtl)
     s = Solver(dim, N, nel, lo, hi, batch=batch, warp=warp, bc=bc, bc_state=bc_state, volume=volume,
-               precision=precision)
+               precision=precision, **kw)
     assert s.E == m.base.E
     return op, s
 
@@ -258,3 +264,88 @@ def test_curvilinear_fp32_statement(volume, case):
     s.rk_stage(to_gpu(s, U0q), to_gpu(s, Uq), out, 0.75, 0.25, 0.002)
     assert rel_err(from_gpu(op, out), rk_stage(op, U0q, Uq, 0.75, 0.25, 0.002)) < 1e-7
     assert s.status()["nonphysical"] == 0
+
+
+# --- Navier-Stokes (BR1) ------------------------------------------------------------
+
+MU = 0.02
+
+
+@pytest.mark.parametrize("N", [2, 3, 4])
+def test_curvilinear_navier_stokes_rhs_parity(N):
+    nel = (4, 3, 3)
+    op, s = pair(3, N, nel, (0.0, 0.0, 0.0), (1.0, 1.3, 0.9), 0.04, mu=MU)
+    U = rand_state(op, 50 + N)
+    ref, spread = rounding_spread(op.rhs, U, nel, half_turns(3))
+    got = from_gpu(op, s.rhs(to_gpu(s, U)))
+    err = spread_err(got, ref, spread)
+    print(f"curvilinear Navier-Stokes N {N}: rel err {rel_err(got, ref):.3e}, err/bound {err:.3f}", flush=True)
+    assert err < 1.0
+
+
+def test_curvilinear_navier_stokes_taylor_green_warped():
+    """The Taylor-Green state (Mach 0.1, mu 6.25e-4) on the [0, 2 pi]^3 box
+    warped by 0.03, 8^3 elements, N = 4: dU/dt against the oracle within the
+    measured rounding floor, a stage, and one SSPRK54 step."""
+    p = di.PRESETS["tgv3d"]
+    nel = (8, 8, 8)
+    op, s = pair(3, 4, nel, p["lo"], p["hi"], 0.03, mu=p["mu"], prandtl=p["prandtl"])
+    U = torch.tensor(di.taylor_green(op.mesh.coords(), mach=p["mach"]))[None]
+    ref, spread = rounding_spread(op.rhs, U, nel, half_turns(3))
+    Ug = to_gpu(s, U)
+    got = from_gpu(op, s.rhs(Ug))
+    err = spread_err(got, ref, spread)
+    print(f"curvilinear Taylor-Green 8^3 N=4: rel err {rel_err(got, ref):.3e}, err/bound {err:.3f}", flush=True)
+    assert err < 1.0
+    dt = 0.2 * s.dt_cfl(Ug, 1.0)
+    out = s.empty()
+    s.rk_stage(None, Ug, out, 0.0, 1.0, dt)
+    # the stage's increment against dt L within the same bound (w = 0 in this
+    # state, so the z-momentum of U + dt L is dt L_z alone)
+    assert spread_err((from_gpu(op, out) - U) / dt, ref, spread) < 1.0
+    Uw = Ug.clone()
+    s.ssprk54_step(Uw, dt)
+    got, want = from_gpu(op, Uw), ssprk54_step(op, U, dt)
+    # density, momentum as one vector, energy
+    groups = [(0,), (1, 2, 3), (4,)]
+    err = max(float((got[:, list(g)] - want[:, list(g)]).abs().max() / want[:, list(g)].abs().max()) for g in groups)
+    assert err < 1e-12
+
+
+def test_curvilinear_navier_stokes_free_stream_conservation_and_stage():
+    op, s = pair(3, 3, (4, 3, 4), (0, 0, 0), (1.0, 1.0, 1.0), 0.05, mu=MU, batch=2)
+    c = s.empty()
+    c[:, 0], c[:, 1], c[:, 2], c[:, 3] = 1.1, 0.33, -0.22, 0.11
+    c[:, 4] = 0.9 / 0.4 + 0.5 * (0.33 ** 2 + 0.22 ** 2 + 0.11 ** 2) / 1.1
+    assert float(s.rhs(c).abs().max()) < 1e-12 * 20.0
+    U = rand_state(op, 9, B=2)
+    dU = s.rhs(to_gpu(s, U))
+    I = s.integrals(dU)[:, :-1]
+    S = s.integrals(dU.abs())[:, :-1]
+    assert np.abs(I / S).max() < 1e-13
+    U0 = rand_state(op, 10, B=2)
+    out = s.empty()
+    s.rk_stage(to_gpu(s, U0), to_gpu(s, U), out, 0.75, 0.25, 0.002)
+    assert rel_err(from_gpu(op, out), rk_stage(op, U0, U, 0.75, 0.25, 0.002)) < TOL64
+
+
+def test_curvilinear_navier_stokes_fp32_statement():
+    op, s = pair(3, 4, (4, 3, 3), (0, 0, 0), (1.0, 1.3, 0.9), 0.04, mu=MU, precision="f32")
+    U = smooth_state(op)
+    Uq = U.float().double()
+    got = from_gpu(op, s.rhs(to_gpu(s, Uq)))
+    ref_q, ref = op.rhs(Uq), op.rhs(U)
+    e_arith, e_quant, e_total = rel_err(got, ref_q), rel_err(ref_q, ref), rel_err(got, ref)
+    print(f"FP32 curvilinear Navier-Stokes: arithmetic {e_arith:.3e}, quantisation floor {e_quant:.3e}, "
+          f"end to end {e_total:.3e}", flush=True)
+    assert e_arith < 1e-5
+    assert e_total <= e_quant + 1e-5
+
+
+def test_curvilinear_navier_stokes_rejections():
+    from paper_2605_26388_amd import Solver
+    from paper_2605_26388_amd._abi import DGError, DG_ERR_UNSUPPORTED
+    for kw in (dict(bc=("wall",) * 6), dict(volume="split")):
+        with pytest.raises(DGError) as e:
+            Solver(3, 3, (2, 2, 2), (0, 0, 0), (1, 1, 1), warp=0.03, physics="navier_stokes", mu=MU, **kw)
+        assert e.value.code == DG_ERR_UNSUPPORTED
