@@ -297,14 +297,14 @@ def bench_large(steps, warmup):
     return res
 
 
-def bench_navier_stokes(reps, nel=None, volume="standard"):
+def bench_navier_stokes(reps, nel=None, volume="standard", warp=0.0):
     from paper_2605_26388_amd import Solver
     p = di.PRESETS["tgv3d"]
     nel = tuple(nel) if nel else tuple(p["nel"])
     out = {}
     for prec in ("f64", "f32"):
         s = Solver(3, p["N"], nel, p["lo"], p["hi"], physics="navier_stokes", precision=prec,
-                   mu=p["mu"], prandtl=p["prandtl"], volume=volume)
+                   mu=p["mu"], prandtl=p["prandtl"], volume=volume, warp=warp)
         X = s.node_coords().cpu().numpy()
         U = torch.tensor(di.taylor_green(X, mach=p["mach"]))[None].to(s.device, s.dtype).contiguous()
         dt = s.dt_cfl(U, p["cfl"])
@@ -315,7 +315,8 @@ def bench_navier_stokes(reps, nel=None, volume="standard"):
         out[prec] = {"ms_per_stage": step / 3 * 1e3, "dof_updates_per_s": 3 * dof / step}
         s.close()
     out["workload"] = (f"tgv3d: Navier-Stokes TGV {nel[0]}^3, N=4, Re 1600, Mach 0.1, BR1 (two passes per stage)"
-                       + (", split-form (Ranocha) inviscid volume integral" if volume == "split" else ""))
+                       + (", split-form (Ranocha) inviscid volume integral" if volume == "split" else "")
+                       + (f", box warped by {warp} (per-node metrics)" if warp else ""))
     return out
 
 
@@ -533,7 +534,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--only", choices=["f64", "f32"], default=None,
                     help="time one form only (profiling runs)")
-    ap.add_argument("--side", choices=["adjoint", "navier_stokes", "navier_stokes_L", "navier_stokes_split", "reacting",
+    ap.add_argument("--side", choices=["adjoint", "navier_stokes", "navier_stokes_L", "navier_stokes_split",
+                                       "navier_stokes_curvilinear", "reacting",
                                        "reacting_2t", "split",
                                        "ssprk54", "curvilinear"],
                     default=None,
@@ -562,6 +564,7 @@ def main():
               "navier_stokes": lambda: bench_navier_stokes(reps),
               "navier_stokes_L": lambda: bench_navier_stokes(reps, nel=(32, 32, 32)),
               "navier_stokes_split": lambda: bench_navier_stokes(reps, volume="split"),
+              "navier_stokes_curvilinear": lambda: bench_navier_stokes(reps, warp=0.03),
               "reacting": lambda: bench_reacting(reps),
               "reacting_2t": lambda: bench_reacting_2t(reps),
               "split": lambda: bench_split(args.steps, args.warmup),
@@ -634,6 +637,7 @@ def main():
         out["navier_stokes"] = bench_navier_stokes(max(5, args.steps // 10))
         out["navier_stokes_L"] = bench_navier_stokes(max(5, args.steps // 10), nel=(32, 32, 32))
         out["navier_stokes_split"] = bench_navier_stokes(max(5, args.steps // 10), volume="split")
+        out["navier_stokes_curvilinear"] = bench_navier_stokes(max(5, args.steps // 10), warp=0.03)
         log("reacting workload ...")
         out["reacting"] = bench_reacting(max(5, args.steps // 10))
         log("two-temperature reacting workload ...")
