@@ -613,8 +613,6 @@ int dg_create(const dg_desc* desc, dg_ctx** out) {
     if (d.physics == DG_NAVIER_STOKES) {
       if (!periodic)
         return fail(DG_ERR_UNSUPPORTED, "curvilinear Navier-Stokes: periodic sides only (no viscous boundary fluxes)");
-      if (d.volume != DG_VOLUME_STANDARD)
-        return fail(DG_ERR_UNSUPPORTED, "curvilinear Navier-Stokes: standard volume integral only");
     } else if (d.physics != DG_EULER) {
       return fail(DG_ERR_UNSUPPORTED, "curvilinear meshes and boundaries: Euler or Navier-Stokes physics only");
     }

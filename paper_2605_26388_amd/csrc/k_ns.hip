@@ -27,15 +27,18 @@
 // term added on the face lanes with the own physical flux), and the surfaces
 // are unchanged.
 //
-// Curvilinear elements (CURV; periodic warped meshes, standard volume
-// integral): per-node metrics 1/J and Ja^l.  The gradient is the strong-form
+// Curvilinear elements (CURV; periodic warped meshes): per-node metrics 1/J
+// and Ja^l.  The gradient is the strong-form
 // operator with the metrics inside the sweep, J S_d = sum_l [sum_m D_im (Ja^l_d
 // W)_m + (+-1/w_end) (W^ - W_i) Ja^l_d,i], staged direction by direction
 // (twelve products Ja^l_d W_q per node); the face buffer holds the
 // contravariant viscous flux Ja^l . F_v of the own face node; pass 2 stages
 // G^l = Ja^l . (F_inv - F_v), takes the Rusanov flux along the own node's
 // Ja^l (as the curvilinear Euler stage) and the central viscous flux of the
-// two buffered contravariant fluxes, and scales by 1/J.
+// two buffered contravariant fluxes, and scales by 1/J; with the split form
+// it stages -Ja^l . F_v for the sweep and every node's Ja^l for the split sum
+// of the curvilinear Euler stage (two-point flux contracted with Ja^l_i +
+// Ja^l_m), whose m = i term -2 D_ii Ja^l . F_inv is added on the face lanes.
 #include <type_traits>
 
 #include "dg_device.hpp"
@@ -87,12 +90,12 @@ k_ns(StageParams sp, MeshView mv, PhysConst pc, T* face, const double* met) {
   constexpr int n = S::n, NP = S::NP, NF = S::NF, EPB = S::EPB, NV = 5;
   using PHYS = EulerPhys<3>;
   constexpr bool SPL = SPLIT && PASS == 2;
-  static_assert(!(SPLIT && CURV), "curvilinear Navier-Stokes: standard volume integral");
 
   __shared__ double sW[CURV ? 12 : 4][EPB * NP];  // W (curvilinear: Ja^l_d W_q of one direction l)
   __shared__ double sF[PASS == 2 ? 3 : 1][NV][PASS == 2 ? EPB * NP : 1];
   __shared__ double sD[n * n];
   __shared__ double sQ[SPL ? 8 : 1][SPL ? EPB * NP : 1];  // split form: rho/2, v/2, p, rho/(2p), ln rho, ln(rho/p)
+  __shared__ double sJ[SPL && CURV ? 9 : 1][SPL && CURV ? EPB * NP : 1];  // curvilinear split: Ja^l_d, row 3l + d
   __shared__ int sFar;
 
   const int tid = threadIdx.x;
@@ -294,11 +297,20 @@ k_ns(StageParams sp, MeshView mv, PhysConst pc, T* face, const double* met) {
 #pragma unroll
       for (int l = 0; l < 3; ++l) {
         double F[NV];
-        normal_flux<3>(u, vel, th.p, Ja[l], F);
-        sF[l][0][tid] = F[0];
+        if constexpr (SPL) {  // only -Ja^l . F_v goes through the D sweep; Ja^l for the partners
+          sF[l][0][tid] = 0.0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          sF[l][1 + q][tid] = F[1 + q] - (Ja[l][0] * Fa[0][q] + Ja[l][1] * Fa[1][q] + Ja[l][2] * Fa[2][q]);
+          for (int q = 0; q < 4; ++q)
+            sF[l][1 + q][tid] = -(Ja[l][0] * Fa[0][q] + Ja[l][1] * Fa[1][q] + Ja[l][2] * Fa[2][q]);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) sJ[3 * l + d][tid] = Ja[l][d];
+        } else {
+          normal_flux<3>(u, vel, th.p, Ja[l], F);
+          sF[l][0][tid] = F[0];
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            sF[l][1 + q][tid] = F[1 + q] - (Ja[l][0] * Fa[0][q] + Ja[l][1] * Fa[1][q] + Ja[l][2] * Fa[2][q]);
+        }
       }
     } else if (tid < S::NT) {
 #pragma unroll
@@ -346,7 +358,9 @@ k_ns(StageParams sp, MeshView mv, PhysConst pc, T* face, const double* met) {
       const double gm1i = 1.0 / gm1;
       bool far = false;
       if (tid < S::NT) {
-        if constexpr (S::BS == 64)
+        if constexpr (CURV)
+          split_sweep_curv<3, N, 0, false>(tid, ii, stride, own, sQ, sJ, Ja, sD, gm1i, far, acc);
+        else if constexpr (S::BS == 64)
           split_sweep_pairs<3, N, 0>(tid, ii, stride, own, sQ, sD, g, gm1i, far, acc);
         else
           split_sweep<3, N, 0, false>(tid, ii, stride, own, sQ, sD, g, gm1i, far, acc);
@@ -362,7 +376,10 @@ k_ns(StageParams sp, MeshView mv, PhysConst pc, T* face, const double* met) {
         if (far) {
 #pragma unroll
           for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-          split_sweep<3, N, 0, true>(tid, ii, stride, own, sQ, sD, g, gm1i, far, acc);
+          if constexpr (CURV)
+            split_sweep_curv<3, N, 0, true>(tid, ii, stride, own, sQ, sJ, Ja, sD, gm1i, far, acc);
+          else
+            split_sweep<3, N, 0, true>(tid, ii, stride, own, sQ, sD, g, gm1i, far, acc);
         }
       }
     }
@@ -448,7 +465,7 @@ k_ns(StageParams sp, MeshView mv, PhysConst pc, T* face, const double* met) {
         for (int c = 0; c < 4; ++c) acc[1 + c] = fma(sc, Dv[1 + c] - (fvn_l[c] - fvo_l[c]), acc[1 + c]);
         if constexpr (SPL) {
           // the split sum's m = i term, 2 D_ii F_l(U_i)
-          const double cd = -2.0 * g[l] * sD[ii[l] * (n + 1)];
+          const double cd = -2.0 * (CURV ? 1.0 : g[l]) * sD[ii[l] * (n + 1)];
 #pragma unroll
           for (int v = 0; v < NV; ++v) acc[v] = fma(cd, Fo[v], acc[v]);
         }
@@ -504,7 +521,10 @@ static hipError_t ns_go(const Ctx& c, const StageParams& sp, hipStream_t s) {
     hipLaunchKernelGGL((k_ns<N, T, 1, false, true>), dim3(nblk), dim3(SH::BS), 0, s, sp, mv, c.pc, face, c.d_met);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_ns<N, T, 2, false, true>), dim3(nblk), dim3(SH::BS), 0, s, sp, mv, c.pc, face, c.d_met);
+    if (c.desc.volume == DG_VOLUME_SPLIT)
+      hipLaunchKernelGGL((k_ns<N, T, 2, true, true>), dim3(nblk), dim3(SH::BS), 0, s, sp, mv, c.pc, face, c.d_met);
+    else
+      hipLaunchKernelGGL((k_ns<N, T, 2, false, true>), dim3(nblk), dim3(SH::BS), 0, s, sp, mv, c.pc, face, c.d_met);
     return hipGetLastError();
   }
   hipLaunchKernelGGL((k_ns<N, T, 1>), dim3(nblk), dim3(SH::BS), 0, s, sp, mv, c.pc, face, nullptr);

@@ -87,8 +87,6 @@ def create(d):
     (dict(bc=(1, 0, 0, 0, 0, 0)), _abi.DG_ERR_ARG, "periodic"),
     (dict(bc=(7, 7, 0, 0, 0, 0)), _abi.DG_ERR_ARG, "dg_bc"),
     (dict(warp=0.05, physics=_abi.DG_NAVIER_STOKES, bc=(2, 2, 0, 0, 0, 0)), _abi.DG_ERR_UNSUPPORTED, "periodic"),
-    (dict(warp=0.05, physics=_abi.DG_NAVIER_STOKES, volume=_abi.DG_VOLUME_SPLIT), _abi.DG_ERR_UNSUPPORTED,
-     "standard"),
     (dict(warp=0.05, physics=_abi.DG_REACTING_EULER, dim=2, nel=(8, 8), mech="air5"), _abi.DG_ERR_UNSUPPORTED,
      "Euler or Navier-Stokes"),
     (dict(dim=2, nel=(8, 8), patch=((2, 2), (4, 4)), bc=(1, 1, 0, 0)), _abi.DG_ERR_UNSUPPORTED, "patch"),
@@ -124,7 +122,8 @@ def test_null_arguments():
                                 dict(warp=0.05, bc=(1, 1, 2, 3, 0, 0), bc_state=(1.0, 0.0, 2.0, 0.0, 5.0)),
                                 dict(warp=0.05, volume=_abi.DG_VOLUME_SPLIT),
                                 dict(warp=0.05, precision=_abi.DG_F32),
-                                dict(warp=0.05, physics=_abi.DG_NAVIER_STOKES, mu=0.01)])
+                                dict(warp=0.05, physics=_abi.DG_NAVIER_STOKES, mu=0.01),
+                                dict(warp=0.05, physics=_abi.DG_NAVIER_STOKES, mu=0.01, volume=_abi.DG_VOLUME_SPLIT)])
 def test_valid_descriptor_passes_the_checks(kw):
     rc, err = create(desc(**kw))
     # no device here: the only failure left is the device query itself

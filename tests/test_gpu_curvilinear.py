@@ -272,30 +272,35 @@ MU = 0.02
 
 
 @pytest.mark.parametrize("N", [2, 3, 4])
-def test_curvilinear_navier_stokes_rhs_parity(N):
+@pytest.mark.parametrize("volume", ["standard", "split"])
+def test_curvilinear_navier_stokes_rhs_parity(N, volume):
     nel = (4, 3, 3)
-    op, s = pair(3, N, nel, (0.0, 0.0, 0.0), (1.0, 1.3, 0.9), 0.04, mu=MU)
+    op, s = pair(3, N, nel, (0.0, 0.0, 0.0), (1.0, 1.3, 0.9), 0.04, mu=MU, volume=volume)
     U = rand_state(op, 50 + N)
     ref, spread = rounding_spread(op.rhs, U, nel, half_turns(3))
     got = from_gpu(op, s.rhs(to_gpu(s, U)))
     err = spread_err(got, ref, spread)
-    print(f"curvilinear Navier-Stokes N {N}: rel err {rel_err(got, ref):.3e}, err/bound {err:.3f}", flush=True)
+    print(f"curvilinear Navier-Stokes {volume} N {N}: rel err {rel_err(got, ref):.3e}, err/bound {err:.3f}",
+          flush=True)
     assert err < 1.0
 
 
-def test_curvilinear_navier_stokes_taylor_green_warped():
+@pytest.mark.parametrize("volume", ["standard", "split"])
+def test_curvilinear_navier_stokes_taylor_green_warped(volume):
     """The Taylor-Green state (Mach 0.1, mu 6.25e-4) on the [0, 2 pi]^3 box
-    warped by 0.03, 8^3 elements, N = 4: dU/dt against the oracle within the
-    measured rounding floor, a stage, and one SSPRK54 step."""
+    warped by 0.03, 8^3 elements, N = 4 (split: the paper's curvilinear
+    viscous setting): dU/dt against the oracle within the measured rounding
+    floor, a stage, and one SSPRK54 step."""
     p = di.PRESETS["tgv3d"]
     nel = (8, 8, 8)
-    op, s = pair(3, 4, nel, p["lo"], p["hi"], 0.03, mu=p["mu"], prandtl=p["prandtl"])
+    op, s = pair(3, 4, nel, p["lo"], p["hi"], 0.03, mu=p["mu"], prandtl=p["prandtl"], volume=volume)
     U = torch.tensor(di.taylor_green(op.mesh.coords(), mach=p["mach"]))[None]
     ref, spread = rounding_spread(op.rhs, U, nel, half_turns(3))
     Ug = to_gpu(s, U)
     got = from_gpu(op, s.rhs(Ug))
     err = spread_err(got, ref, spread)
-    print(f"curvilinear Taylor-Green 8^3 N=4: rel err {rel_err(got, ref):.3e}, err/bound {err:.3f}", flush=True)
+    print(f"curvilinear Taylor-Green {volume} 8^3 N=4: rel err {rel_err(got, ref):.3e}, err/bound {err:.3f}",
+          flush=True)
     assert err < 1.0
     dt = 0.2 * s.dt_cfl(Ug, 1.0)
     out = s.empty()
@@ -345,7 +350,7 @@ def test_curvilinear_navier_stokes_fp32_statement():
 def test_curvilinear_navier_stokes_rejections():
     from paper_2605_26388_amd import Solver
     from paper_2605_26388_amd._abi import DGError, DG_ERR_UNSUPPORTED
-    for kw in (dict(bc=("wall",) * 6), dict(volume="split")):
+    for kw in (dict(bc=("wall",) * 6),):
         with pytest.raises(DGError) as e:
             Solver(3, 3, (2, 2, 2), (0, 0, 0), (1, 1, 1), warp=0.03, physics="navier_stokes", mu=MU, **kw)
         assert e.value.code == DG_ERR_UNSUPPORTED
