@@ -140,6 +140,18 @@ __device__ __forceinline__ void normal_flux(const double (&U)[DIM + 2], const do
   F[DIM + 1] = (U[DIM + 1] + p) * vn;
 }
 
+// Single-wave workgroups: LDS accesses of a wave complete in order, so a
+// wave-level fence (no barrier) orders one lane's LDS writes before another
+// lane's reads and keeps the compiler from moving them across.
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// an LDS address for the buffer-to-LDS load builtin
+#define DG_LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
+
 // Make a value the compiler cannot prove uniform a scalar (only valid when it
 // is uniform across the wave).
 __device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }

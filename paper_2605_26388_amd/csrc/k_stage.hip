@@ -396,14 +396,6 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
 // flux minus the element's first-node flux rounded to float, float sweep,
 // accumulator and stage combination).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void wave_lds_fence() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-#define DG_LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
-
 // double value of lane 0 (wave-uniform)
 __device__ __forceinline__ double lane0(double x) {
   const u32x2 w = __builtin_bit_cast(u32x2, x);
