@@ -14,8 +14,9 @@ and vortex convergence.  BR1 viscous terms with per-node metrics: reduction to
 the Cartesian Navier-Stokes operator at zero warp, free stream and
 conservation on warped meshes (both volume forms), the lifted gradient
 integrating to zero on a periodic mesh (and not with the face terms' sign
-flipped), and convergence of the viscous term to its exact value for a
-manufactured state at the Cartesian operator's rate."""
+flipped), convergence of the viscous term to its exact value for a
+manufactured state at the Cartesian operator's rate, and the Taylor-Green
+dissipation rate -3/4 mu approached on a warped box."""
 
 import math
 
@@ -438,3 +439,29 @@ def test_br1_gradient_integrates_to_zero(dim, N):
 
     assert totals(CurvOperator) < 1e-13
     assert totals(_LiftSignFlipped) > 1e-3
+
+
+def test_taylor_green_dissipation_rate_on_warped_box():
+    """The Taylor-Green initial state on the [0, 2 pi]^3 box warped by 0.03,
+    N = 4: the kinetic-energy rate of the right-hand side converges to the
+    exact -3/4 mu (the viscous dissipation of the initial field; the
+    inviscid part, both volume forms, is zero to round-off since the state
+    is continuous and divergence-free): relative deviation 8.8e-6 on 4^3 and
+    7.6e-8 on 8^3 as measured."""
+    P = di.PRESETS["tgv3d"]
+    vis = dict(mu=P["mu"], prandtl=P["prandtl"], gamma=G)
+    devs = []
+    for nel in (4, 8):
+        m = CurvMesh(3, 4, (nel,) * 3, P["lo"], P["hi"], 0.03)
+        U = torch.tensor(di.taylor_green(m.coords(), mach=P["mach"]))[None]
+        wJ = weights(m)
+        vel = U[:, 1:4] / U[:, 0:1]
+
+        def rate(dU):
+            ke = (vel * dU[:, 1:4]).sum(1) - 0.5 * (vel * vel).sum(1) * dU[:, 0]
+            return float((wJ[None] * ke).sum()) / (2 * math.pi) ** 3
+
+        for volume in ("standard", "split"):
+            assert abs(rate(CurvOperator(m, volume=volume).rhs(U))) < 1e-11 * P["mu"]
+        devs.append(abs(rate(CurvOperator(m, viscous=vis).rhs(U)) / (-0.75 * P["mu"]) - 1.0))
+    assert devs[1] < 1e-6 and devs[0] > 30 * devs[1], devs
