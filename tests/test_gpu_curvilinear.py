@@ -354,3 +354,29 @@ def test_curvilinear_navier_stokes_rejections():
         with pytest.raises(DGError) as e:
             Solver(3, 3, (2, 2, 2), (0, 0, 0), (1, 1, 1), warp=0.03, physics="navier_stokes", mu=MU, **kw)
         assert e.value.code == DG_ERR_UNSUPPORTED
+
+
+@pytest.mark.skipif(__import__("os").environ.get("DG_LONG", "0") != "1",
+                    reason="full-length run (a minute of CPU oracle time): set DG_LONG=1")
+@pytest.mark.parametrize("volume", ["standard", "split"])
+def test_curvilinear_taylor_green_50_steps(volume):
+    """The warped Taylor-Green case (8^3, N = 4, warp 0.03) advanced 50
+    SSP-RK3 steps by the library (FP64) and by the oracle: each of the 150
+    stages adds at most dt times the right-hand side's rounding-floor bound,
+    so 1e-11 of each variable group's norm (momentum as one vector) covers
+    the run."""
+    from oracle.timestep import ssprk33_step
+    p = di.PRESETS["tgv3d"]
+    op, s = pair(3, 4, (8, 8, 8), p["lo"], p["hi"], 0.03, mu=p["mu"], prandtl=p["prandtl"], volume=volume)
+    U = torch.tensor(di.taylor_green(op.mesh.coords(), mach=p["mach"]))[None]
+    Ug = to_gpu(s, U)
+    dt = s.dt_cfl(Ug, p["cfl"])
+    groups = [(0,), (1, 2, 3), (4,)]
+    for k in range(50):
+        U = ssprk33_step(op, U, dt)
+        s.ssprk3_step(Ug, dt)
+    got = from_gpu(op, Ug)
+    err = max(float((got[:, list(g)] - U[:, list(g)]).abs().max() / U[:, list(g)].abs().max()) for g in groups)
+    print(f"curvilinear Taylor-Green {volume} after 50 steps: {err:.3e}", flush=True)
+    assert err < 1e-11
+    assert s.status()["nonphysical"] == 0
