@@ -325,4 +325,62 @@ __device__ __forceinline__ void split_sweep_curv(int tid, const int (&ii)[3], co
   }
 }
 
+// The pairwise form of split_sweep_curv for lines inside one wave: each
+// unordered pair's flux F# . (Ja^l_i + Ja^l_m) is evaluated once (flux and
+// metric sum are both symmetric in the pair) and handed to the partner lane
+// by a shuffle, as in split_sweep_pairs.
+template <int DIM, int N, int l, int W>
+__device__ __forceinline__ void split_sweep_pairs_curv(int tid, const int (&ii)[3], const int (&stride)[3],
+                                                       const SplitNode<DIM>& a, const double (*Q)[W],
+                                                       const double (*Jm)[W], const double (&Ja)[DIM][DIM],
+                                                       const double* sD, double gm1i, bool& far,
+                                                       double (&acc)[DIM + 2]) {
+  if constexpr (l < DIM) {
+    constexpr int NV = DIM + 2, n = N + 1, K1 = (n - 1) / 2;
+    const int il = ii[l];
+    const int st = stride[l];
+    const int base = tid - il * st;
+    const int lbase = (tid & 63) - il * st;  // wave lane of the line's node 0
+    double s[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) s[v] = 0.0;
+    auto flux = [&](int m, bool& fl, double (&F)[NV]) {
+      double nv[DIM];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) nv[d] = Ja[l][d] + Jm[l * DIM + d][m];
+      ranocha_flux_n<DIM, false>(a, Q, tid, m, nv, gm1i, fl, F);
+    };
+#pragma unroll
+    for (int k = 1; k <= K1; ++k) {
+      const int m = il + k < n ? il + k : il + k - n;   // partner evaluated here
+      const int j = il - k >= 0 ? il - k : il - k + n;  // partner whose flux arrives
+      double F[NV];
+      bool fp = false;
+      flux(base + m * st, fp, F);
+      const double dm = sD[il * n + m];
+      const double dj = sD[il * n + j];
+      const int src = lbase + j * st;
+      const int fr = __shfl(fp ? 1 : 0, src);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double Fr = __shfl(F[v], src);
+        s[v] = fma(dm, F[v], s[v]);
+        s[v] = fma(dj, Fr, s[v]);
+      }
+      far = far || fp || fr != 0;
+    }
+    if constexpr (n % 2 == 0) {
+      const int m = il + n / 2 < n ? il + n / 2 : il - n / 2;
+      double F[NV];
+      flux(base + m * st, far, F);
+      const double dm = sD[il * n + m];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) s[v] = fma(dm, F[v], s[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] -= s[v];
+    split_sweep_pairs_curv<DIM, N, l + 1>(tid, ii, stride, a, Q, Jm, Ja, sD, gm1i, far, acc);
+  }
+}
+
 }  // namespace dg

@@ -156,7 +156,12 @@ k_stage_curv(StageParams sp, MeshView mv, PhysConst pc, CurvArgs ca) {
   if constexpr (SPLIT) {
     const double gm1i = 1.0 / (pc.gamma - 1.0);
     bool far = false;
-    if (tid < S::NT) split_sweep_curv<DIM, N, 0, false>(tid, ii, stride, own, sQ, sJ, Ja, sD, gm1i, far, acc);
+    if (tid < S::NT) {
+      if constexpr (S::BS == 64)  // lines inside one wave: each pair once, handed over by a shuffle
+        split_sweep_pairs_curv<DIM, N, 0>(tid, ii, stride, own, sQ, sJ, Ja, sD, gm1i, far, acc);
+      else
+        split_sweep_curv<DIM, N, 0, false>(tid, ii, stride, own, sQ, sJ, Ja, sD, gm1i, far, acc);
+    }
     if (far) sFar = 1;
     __syncthreads();
     if (sFar) {  // block-uniform: some pair is too far apart for the series
