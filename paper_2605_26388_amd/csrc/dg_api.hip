@@ -509,7 +509,7 @@ __global__ void k_reset_counters(int* cnt, unsigned long long* first_bad) {
 void free_ctx(Ctx& c) {
   void* ptrs[] = {c.d_nbr, c.d_geo, c.d_K, c.d_counters, c.d_first_bad, c.d_mortars,
                   c.d_mortar_flux, c.d_red, c.d_red_out, c.d_face, c.d_mech, c.d_vib, c.d_corner,
-                  c.d_met, c.d_xyz};
+                  c.d_met, c.d_xyz, c.d_defer, c.d_defer_count};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -742,6 +742,18 @@ int dg_create(const dg_desc* desc, dg_ctx** out) {
       free_ctx(c);
       delete ctx;
       return e == hipErrorOutOfMemory ? fail(DG_ERR_OOM, "BR1 face buffer") : hip_fail(e, "dg_create face buffer");
+    }
+  }
+  if (d.physics == DG_REACTING_EULER) {
+    // one record per node for the nodes whose implicit substep takes the
+    // continuation in h (a node index and its iteration count, 8 bytes)
+    const size_t bytes = (size_t)c.B * c.E * c.Np * 8;
+    if ((e = upload(&c.d_defer, nullptr, bytes)) != hipSuccess ||
+        (e = upload(&c.d_defer_count, nullptr, sizeof(int))) != hipSuccess) {
+      free_ctx(c);
+      delete ctx;
+      return e == hipErrorOutOfMemory ? fail(DG_ERR_OOM, "chemistry continuation list")
+                                      : hip_fail(e, "dg_create continuation list");
     }
   }
   hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, 0, c.d_counters, c.d_first_bad);

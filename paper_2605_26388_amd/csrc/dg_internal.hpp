@@ -102,6 +102,10 @@ struct Ctx {
   size_t red_cap = 0;            // doubles
   double* d_red_out = nullptr;   // final reduction results
   void* d_face = nullptr;        // BR1 face buffer
+  // implicit chemistry substep: nodes handed from the first pass to the
+  // continuation pass ([B*E*Np] records) and their count
+  void* d_defer = nullptr;
+  int* d_defer_count = nullptr;
   void* d_mech = nullptr;        // mechanism copy on device
   void* d_vib = nullptr;         // vibrational data on device (two-temperature)
   // curvilinear meshes: metric planes [2 + dim*dim][E*Np] (J, 1/J, Ja^l_d at

@@ -22,7 +22,10 @@
 //   spurious corner with a species at zero); it counts as unconverged only if
 //   the last level does not converge.  The state of a node never leaves
 //   registers between evaluations; global traffic is one read and one write
-//   of the state.
+//   of the state.  The substep runs in two passes: the first makes every
+//   node's Newton iteration at h and hands the nodes that need the
+//   continuation (a node index and its iteration count) to the second, which
+//   runs each of them on a group of eight lanes (k_source_cont below).
 #include <algorithm>
 
 #include "dg_device.hpp"
@@ -140,10 +143,17 @@ __device__ __forceinline__ void gauss_jordan(double (&A)[NS][NS], double (&b)[NS
   for (int i = 0; i < NS; ++i) x[i] = b[i];
 }
 
+// A node whose implicit substep takes the continuation in h, handed from the
+// first pass to the second: its flat node index and the iterations spent.
+struct DeferredNode {
+  unsigned t;
+  int it;
+};
+
 template <typename T, int NS, int NR, int DIM>
 __global__ void __launch_bounds__(256)
 k_source(const T* U, T* out, const dg_mechanism* mech, size_t plane, int B, double h, int mode, int max_iter,
-         double tol, int* counters, unsigned long long* first_bad) {
+         double tol, int* counters, unsigned long long* first_bad, DeferredNode* defer, int* defer_count) {
   constexpr int NV = NS + DIM + 1;
   const Chem<NS, NR> chem{mech};
   const size_t total = plane * B;
@@ -237,6 +247,18 @@ k_source(const T* U, T* out, const dg_mechanism* mech, size_t plane, int B, doub
       return false;
     };
     bool converged = newton(h);
+    if (!converged && !nonphys && defer) {
+      // the continuation runs in the second pass, on a group of lanes: hand
+      // the node over with its iteration count (its species are written there)
+      defer[atomicAdd(defer_count, 1)] = DeferredNode{static_cast<unsigned>(t), it};
+      if (clips) atomicAdd(&counters[CNT_CLIPS], clips);
+      if (out != U) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) out[base + (NS + d) * plane] = static_cast<T>(mom[d]);
+        out[base + (NS + DIM) * plane] = static_cast<T>(E);
+      }
+      continue;
+    }
     if (!converged && !nonphys) {
 #pragma unroll
       for (int s = 0; s < NS; ++s) Y[s] = Yn[s];
@@ -254,6 +276,130 @@ k_source(const T* U, T* out, const dg_mechanism* mech, size_t plane, int B, doub
       out[base + (NS + DIM) * plane] = static_cast<T>(E);
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Second pass of the implicit substep: the continuation in h of the nodes the
+// first pass handed over, one node per group of G = 8 lanes.  In each Newton
+// iteration the six residual evaluations (the base point on lane NS, the
+// point displaced along Y_k on lane k) run side by side and are exchanged by
+// lane shuffles; every lane of the group then forms the same difference
+// Jacobian and solves the same system, so the iterates are those of the
+// one-lane iteration bit for bit, while an iteration takes about one
+// evaluation's latency instead of six.  The few nodes that need the
+// continuation (a few per cent at the surveyed stiffness, up to 40 levels of
+// Newton solves) otherwise keep their whole wave waiting.
+// ---------------------------------------------------------------------------
+template <typename T, int NS, int NR, int DIM>
+__global__ void __launch_bounds__(256)
+k_source_cont(const T* U, T* out, const dg_mechanism* mech, size_t plane, double h, int max_iter, double tol,
+              int* counters, unsigned long long* first_bad, const DeferredNode* defer, const int* defer_count) {
+  constexpr int G = 8, NV = NS + DIM + 1;
+  static_assert(NS + 1 <= G, "one lane per Jacobian column and one for the base point");
+  const Chem<NS, NR> chem{mech};
+  const int lane = threadIdx.x & (G - 1);
+  const int count = *defer_count;
+  const int groups = (int)(((size_t)gridDim.x * blockDim.x) / G);
+  for (int g = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / G); g < count; g += groups) {
+    const DeferredNode dn = defer[g];
+    const size_t t = dn.t;
+    const size_t b = t / plane;
+    const size_t r = t - b * plane;
+    const size_t base = b * NV * plane + r;
+    double Yn[NS];
+    double rho = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      Yn[s] = static_cast<double>(U[base + s * plane]);
+      rho += Yn[s];
+    }
+    double m2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const double md = static_cast<double>(U[base + (NS + d) * plane]);
+      m2 += md * md;
+    }
+    const double E = static_cast<double>(U[base + (NS + DIM) * plane]);
+    const double ke = 0.5 * m2 / rho;
+    double Y[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) Y[s] = Yn[s];
+    int it = dn.it, clips = 0;
+    bool nonphys = false;
+    auto newton = [&](double hh) -> bool {
+      for (int k_it = 0; k_it < max_iter; ++k_it) {
+        // this lane's point: Y displaced along Y_lane (lanes < NS), else Y
+        double Yp[NS], eps = 1.0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          Yp[s] = Y[s];
+          if (s == lane) {
+            eps = fmax(1e-7 * fabs(Y[s]), 1e-12);
+            Yp[s] = Yp[s] + eps;
+          }
+        }
+        double Rl[NS];
+        const double Tl = chem.residual(Yp, Yn, hh, ke, E, Rl);
+        double R0[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) R0[s] = __shfl(Rl[s], NS, G);
+        const double T0 = __shfl(Tl, NS, G);
+        if (!(T0 > 0.0)) {
+          nonphys = true;
+          return false;
+        }
+        ++it;
+        double J[NS][NS];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          const double ek = __shfl(eps, k, G);
+#pragma unroll
+          for (int s = 0; s < NS; ++s) J[s][k] = (__shfl(Rl[s], k, G) - R0[s]) / ek;
+        }
+        double rhs[NS], dY[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) rhs[s] = -R0[s];
+        gauss_jordan<NS>(J, rhs, dY);
+        double alpha = 1.0;
+        for (int hv = 0; hv < 30; ++hv) {
+          double Yt[NS];
+#pragma unroll
+          for (int s = 0; s < NS; ++s) Yt[s] = fmax(Y[s] + alpha * dY[s], 0.0);
+          const double Tt = chem.temperature(Yt, ke, E);
+          if (!(Tt < 0.5 * T0) && !(Tt > 2.0 * T0)) break;
+          alpha *= 0.5;
+        }
+        double dmax = 0.0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          dY[s] = alpha * dY[s];
+          double y = Y[s] + dY[s];
+          if (y < 0.0) {
+            ++clips;
+            y = 0.0;
+          }
+          Y[s] = y;
+          dmax = fmax(dmax, fabs(dY[s]));
+        }
+        if (alpha == 1.0 && dmax <= tol * rho) return true;
+      }
+      return false;
+    };
+    bool converged = false;
+    for (int j = CONT_LEVELS; j >= 0 && !nonphys; --j) converged = newton(ldexp(h, -j));
+    if (lane == 0) {
+      if (nonphys) report_nonphysical(counters, first_bad, t);
+      if (!converged) atomicAdd(&counters[CNT_NEWTON], 1);
+      if (clips) atomicAdd(&counters[CNT_CLIPS], clips);
+      atomicMax(&counters[CNT_ITERS], it);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) out[base + s * plane] = static_cast<T>(Y[s]);
+    }
+  }
+}
+
+__global__ void k_zero_count(int* p) {
+  if (threadIdx.x == 0) *p = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -589,14 +735,36 @@ hipError_t launch_source(const Ctx& c, const void* U, void* out, double h, int m
                          c.desc.newton_tol, c.d_counters, c.d_first_bad);
     return hipGetLastError();
   }
-  if (c.desc.precision == DG_F32)
+  // mode 1 in two passes: the first runs every node's Newton iteration at h
+  // and hands the nodes that need the continuation to the second
+  const bool two_pass = mode == 1 && c.d_defer && total < ((size_t)1 << 31);
+  DeferredNode* defer = two_pass ? static_cast<DeferredNode*>(c.d_defer) : nullptr;
+  if (two_pass) {
+    hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(64), 0, s, c.d_defer_count);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  // the second pass: 32 nodes per 256-lane block, grid-stride beyond 1024 blocks
+  const int cont_blocks = (int)std::min<size_t>((total + 31) / 32, 1024);
+  if (c.desc.precision == DG_F32) {
     hipLaunchKernelGGL((k_source<float, 5, 5, 2>), dim3(blocks), dim3(256), 0, s, static_cast<const float*>(U),
                        static_cast<float*>(out), m, plane, c.B, h, mode, c.desc.newton_max_iter, c.desc.newton_tol,
-                       c.d_counters, c.d_first_bad);
-  else
+                       c.d_counters, c.d_first_bad, defer, c.d_defer_count);
+    if (two_pass)
+      hipLaunchKernelGGL((k_source_cont<float, 5, 5, 2>), dim3(cont_blocks), dim3(256), 0, s,
+                         static_cast<const float*>(U), static_cast<float*>(out), m, plane, h,
+                         c.desc.newton_max_iter, c.desc.newton_tol, c.d_counters, c.d_first_bad, defer,
+                         c.d_defer_count);
+  } else {
     hipLaunchKernelGGL((k_source<double, 5, 5, 2>), dim3(blocks), dim3(256), 0, s, static_cast<const double*>(U),
                        static_cast<double*>(out), m, plane, c.B, h, mode, c.desc.newton_max_iter, c.desc.newton_tol,
-                       c.d_counters, c.d_first_bad);
+                       c.d_counters, c.d_first_bad, defer, c.d_defer_count);
+    if (two_pass)
+      hipLaunchKernelGGL((k_source_cont<double, 5, 5, 2>), dim3(cont_blocks), dim3(256), 0, s,
+                         static_cast<const double*>(U), static_cast<double*>(out), m, plane, h,
+                         c.desc.newton_max_iter, c.desc.newton_tol, c.d_counters, c.d_first_bad, defer,
+                         c.d_defer_count);
+  }
   return hipGetLastError();
 }
 
