@@ -106,6 +106,31 @@ def test_implicit_substep_parity_full_workload():
     assert st["newton_iters_max"] <= 25 * 42
 
 
+def test_implicit_substep_fp32_in_place():
+    """The two-pass implicit substep with a float state (double arithmetic)
+    and in place (out = U) on the full workload: the species against the
+    oracle at the float-rounded state to the float rounding of the output,
+    the continued nodes included; momentum and energy untouched."""
+    mech = di.preset_mechanism(P)
+    op, s = make_pair(2, 3, P["nel"], P["lo"], P["hi"], physics="reacting", patch=(P["patch_lo"], P["patch_hi"]),
+                      mech=mech, precision="f32")
+    U = torch.tensor(di.reacting_state(op.mesh.coords(), P["lo"], P["hi"], mech))[None].float().double()
+    Ug = to_gpu(s, U)
+    h = 0.5 * dt_cfl(op, U, P["cfl"])
+    s.status(reset=True)
+    s.source_chem(Ug, Ug, h, 1)
+    st = s.status(reset=True)
+    ref, info = chem.implicit_substep(mech, 2, U, h)
+    assert info["continued"] > 0 and info["unconverged"] == 0
+    assert st["newton_unconverged"] == 0 and st["nonphysical"] == 0
+    got = from_gpu(op, Ug)
+    rho = U[:, :5].sum(1, keepdim=True)
+    err = float(((got[:, :5] - ref[:, :5]).abs() / rho).max())
+    print(f"FP32 implicit substep in place: species {err:.3e} of rho", flush=True)
+    assert err < 2e-7
+    assert torch.equal(got[:, 5:], U[:, 5:])
+
+
 def test_strang_step_matches_oracle():
     """Two Strang steps S_{dt/2} T_dt S_{dt/2} on the full reacting workload
     (quiescent initial state, dt at CFL 0.5; the implicit substeps converge
