@@ -191,6 +191,30 @@ def cpu_baseline(p, budget_s=15.0):
                 f"torch-CPU float64 on {threads} threads of {cpu_model()}; plus one stage on 1 thread")
 
 
+def copy_ceiling(nbytes, reps=20):
+    """Bandwidth of a plain device copy (torch's elementwise copy kernel) of
+    nbytes into a second buffer: bytes read plus bytes written over the GPU
+    time of one copy (HIP events around `reps` back-to-back copies, after
+    warm-up copies) -- the practical ceiling of a streaming kernel at that
+    footprint."""
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / t / 1e9
+
+
 def cpu_model():
     """The host CPU's model name (from /proc/cpuinfo), else the machine type."""
     try:
@@ -628,6 +652,15 @@ def main():
         "steady_state": steady_summary(res, "after >= 0.2 s more of back-to-back steps (the clock the device "
                                             "sustains under this load); the headline is the measurement above"),
     }
+    # the practical ceiling: a plain copy moving the stage's algorithmic bytes
+    # (read half, write half; cache-resident like the stage) and one of 1 GiB
+    # per buffer (past the Infinity Cache), after the headline measurement
+    c_stage = copy_ceiling(int(f64["bytes"]) // 2 // 8 * 8)
+    c_large = copy_ceiling(1 << 30)
+    out["roofline"]["copy_ceiling"] = {
+        "gbs_at_stage_bytes": c_stage, "gbs_1gib": c_large,
+        "frac_of_copy_at_stage_bytes": achieved / c_stage,
+        "note": "torch's device copy; bytes read + written per copy over its GPU time"}
     if not args.no_extras:
         log("64^3 workload ...")
         out["euler3d_L"] = bench_large(args.steps, args.warmup)
