@@ -383,18 +383,36 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
 //     face, 16-31 the +xi_l face, tangential index a + 4 b in the two other
 //     directions);
 //   * U0, when the stage reads it: FP64 into registers right after those
-//     loads (96 VGPRs, 5 waves per SIMD, and the LDS stays at 6.8 KB so it
-//     does not limit the waves either -- measured faster than loading it into
-//     LDS), FP32 into LDS by one 4-byte load per variable.
-// The directions are then processed one after the other: the flux along l
-// is staged in LDS, swept with D (scaled by -2/h_l), and the lanes on an l
-// face apply their interface correction with the own flux still in
-// registers.  Being one wave, the workgroup needs no barrier: LDS accesses of
-// a wave complete in order, and a wave-level fence keeps the compiler from
-// reordering them.  Same arithmetic per term as k_stage, including the FP32
-// form's conventions (fluxes and face corrections in double, the staged
-// flux minus the element's first-node flux rounded to float, float sweep,
-// accumulator and stage combination).
+//     loads (the LDS stays at 6.8 KB so it does not limit the waves per
+//     SIMD -- measured faster than loading it into LDS), FP32 into LDS by
+//     one 4-byte load per variable.
+// The directions are then processed one after the other, each followed by
+// the interface correction of the lanes on its faces (own flux still in
+// registers).  Along x and y the flux is staged in LDS and swept with D
+// (scaled by -2/h_l).  Along z the contraction is one FP64 matrix-core
+// instruction per variable: the 4-block 4x4x4 MFMA multiplies, in block b,
+// A[i][k] held by lane i + 4b + 16k with B[k][n] held by lane n + 4b + 16k
+// and accumulates into C[i][n] held by lane n + 4b + 16i.  With node index
+// x + 4y + 16z on the lane, B = the lane's own flux (k = z, n = x, b = y),
+// A = the scaled D entry D[i][k] of lane i + 4b + 16k, and C = the lane's own
+// accumulator (i = z): the z sweep needs no data movement at all, which
+// takes a third of the sweep's LDS traffic and FMAs off the shared LDS and
+// vector pipes.  Being one wave, the workgroup needs no barrier: LDS
+// accesses of a wave complete in order, and a wave-level fence keeps the
+// compiler from reordering them.
+//
+// FP32 form: fluxes and face corrections in double, the x and y fluxes
+// staged as float differences from the element's first-node flux (D
+// annihilates constants, so the sum is unchanged and the rounding error is
+// relative to the variation inside the element), float sweeps and
+// accumulator; the z contraction in double on the matrix core, rounded once
+// into the accumulator.
+//
+// The interface correction of a lane on the s face of direction l
+// (s = +1 on the +xi_l face, -1 on the -xi_l face) is the Rusanov
+// difference 2 (F* - F_own) = (F_nb - F_own) - s lam (U_nb - U_own) times
+// -s (2/h_l) / (2 w_end); with c = (2/h_l) / (2 w_end) it is
+//     c lam (U_nb - U_own) - s c (F_nb - F_own).
 // ---------------------------------------------------------------------------
 // double value of lane 0 (wave-uniform)
 __device__ __forceinline__ double lane0(double x) {
@@ -414,12 +432,14 @@ k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
   constexpr int CP = NT ? CPOL_NT : 0;  // policy of the streams no other workgroup reads: U0 and the output
   constexpr int WPV = F32 ? 32 : 64;  // dwords of face data per direction and variable
   __shared__ T sF[NV][NP];
-  __shared__ T sDg[DIM][n * n];
+  __shared__ T sDg[2][n * n];
   __shared__ __attribute__((aligned(16))) unsigned sNb[DIM][NV][WPV];
   __shared__ __attribute__((aligned(16))) T sU0[F32 ? NV : 1][F32 ? NP : 1];
 
   const int tid = threadIdx.x;
   const double dsc = tid < n * n ? mv.K->D[tid] : 0.0;
+  // matrix-core operand of the z sweep: D[i][k] on lane i + 4b + 16k
+  const double dz = mv.K->D[(tid & 3) * n + (tid >> 4)];
   const int E = mv.E;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int b = blk / E;
@@ -488,62 +508,78 @@ k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
   const double aown = wave_sound<PHYS, F32>(th);
   if (tid < n * n) {
 #pragma unroll
-    for (int l = 0; l < DIM; ++l) sDg[l][tid] = static_cast<T>(-g[l] * dsc);
+    for (int l = 0; l < 2; ++l) sDg[l][tid] = static_cast<T>(-g[l] * dsc);
   }
+  const double az = -g[2] * dz;
+  // byte offset of this lane's slot in sNb[l][v] for each direction l, one
+  // byte per direction (meaningful on the lanes of an l face, whose face
+  // side is the low bit of their index along l):
+  //   x: slot 16 (i & 1) + j + 4 k,  y: 16 (j & 1) + i + 4 k,  z: 16 (k & 1) + i + 4 j
+  const unsigned sx = ((tid & 1) << 4) | (tid >> 2);
+  const unsigned sy = (((tid >> 2) & 1) << 4) | (tid & 3) | ((tid >> 4) << 2);
+  const unsigned sz = (((tid >> 4) & 1) << 4) | (tid & 15);
+  constexpr unsigned SB = F32 ? 2 : 3;  // log2 of the bytes of one slot
+  const unsigned fslots = (sx << SB) | ((sy << SB) << 8) | ((sz << SB) << 16);
 
   T acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = T(0);
 #pragma unroll
   for (int l = 0; l < DIM; ++l) {
+    const int il = ii[l];
     double F[NV];
     PHYS::flux(u, vel[l], th.p, l, F);
+    if (l < 2) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      // FP32: relative to the element's first node (D annihilates constants)
-      if constexpr (F32) sF[v][tid] = static_cast<float>(F[v] - lane0(F[v]));
-      else sF[v][tid] = F[v];
+      for (int v = 0; v < NV; ++v) {
+        // FP32: relative to the element's first node (D annihilates constants)
+        if constexpr (F32) sF[v][tid] = static_cast<float>(F[v] - lane0(F[v]));
+        else sF[v][tid] = F[v];
+      }
+      wave_lds_fence();
+      // volume integral along l
+      const int st = stride[l], base = tid - il * st;
+      T drow[n];
+#pragma unroll
+      for (int m = 0; m < n; ++m) drow[m] = sDg[l][il * n + m];
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int m = 0; m < n; ++m) acc[v] = fma(drow[m], sF[v][base + m * st], acc[v]);
+    } else {
+      // volume integral along z on the matrix core
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        if constexpr (F32) acc[v] += static_cast<float>(__builtin_amdgcn_mfma_f64_4x4x4f64(az, F[v], 0.0, 0, 0, 0));
+        else acc[v] = __builtin_amdgcn_mfma_f64_4x4x4f64(az, F[v], acc[v], 0, 0, 0);
+      }
     }
-    wave_lds_fence();
-    // volume integral along l
-    const int il = ii[l], st = stride[l], base = tid - il * st;
-    T drow[n];
-#pragma unroll
-    for (int m = 0; m < n; ++m) drow[m] = sDg[l][il * n + m];
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-#pragma unroll
-      for (int m = 0; m < n; ++m) acc[v] = fma(drow[m], sF[v][base + m * st], acc[v]);
-    // surface correction on the l faces: 2 (F* - F_own) = (F_nb - F_own) - s lam (U_nb - U_own)
-    const int side = (il == 0) ? 0 : ((il == N) ? 1 : -1);
-    if (side >= 0) {
-      const int o1 = l == 0 ? 1 : 0, o2 = l == 2 ? 1 : 2;
-      const int slot = side * 16 + ii[o1] + 4 * ii[o2];
+    // interface correction on the l faces
+    if (il == 0 || il == N) {
+      const unsigned so = (fslots >> (8 * l)) & 0xffu;
       double un[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        if constexpr (F32) un[v] = static_cast<double>(__builtin_bit_cast(float, sNb[l][v][slot]));
-        else un[v] = *reinterpret_cast<const double*>(&sNb[l][v][2 * slot]);
+        const char* p = reinterpret_cast<const char*>(&sNb[l][v][0]) + so;
+        if constexpr (F32) un[v] = static_cast<double>(*reinterpret_cast<const float*>(p));
+        else un[v] = *reinterpret_cast<const double*>(p);
       }
       Thermo tn;
       PHYS::thermo(un, tn, pc);
       const double vn = un[1 + l] * tn.ri;
       double Fn[NV];
       PHYS::flux(un, vn, tn.p, l, Fn);
-      const double co = fabs(vel[l]) + aown;
-      const double cn = fabs(vn) + wave_sound<PHYS, F32>(tn);
-      const double lam = fmax(co, cn);
-      const double sgn = side == 1 ? 1.0 : -1.0;
-      const double hs = sgn * lam;
-      const double sc = -sgn * (g[l] * hwinv);
+      const double lam = fmax(fabs(vel[l]) + aown, fabs(vn) + wave_sound<PHYS, F32>(tn));
+      const double c = g[l] * hwinv;
+      const double cl = c * lam;
+      const double cs = (il == N) ? -c : c;
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        const double dv = fma(-hs, un[v] - u[v], Fn[v] - F[v]);
-        if constexpr (F32) acc[v] = fma(static_cast<float>(sc), static_cast<float>(dv), acc[v]);
-        else acc[v] = fma(sc, dv, acc[v]);
+        if constexpr (F32) acc[v] += static_cast<float>(fma(cs, Fn[v] - F[v], cl * (un[v] - u[v])));
+        else acc[v] = fma(cs, Fn[v] - F[v], fma(cl, un[v] - u[v], acc[v]));
       }
     }
-    wave_lds_fence();  // the next direction overwrites sF
+    if (l < 2) wave_lds_fence();  // the next direction overwrites sF
   }
 
   // ---- output ----------------------------------------------------------------
