@@ -383,30 +383,43 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
 //     face, 16-31 the +xi_l face, tangential index a + 4 b in the two other
 //     directions);
 //   * U0, when the stage reads it: FP64 into registers right after those
-//     loads (the LDS stays at 6.8 KB so it does not limit the waves per
-//     SIMD -- measured faster than loading it into LDS), FP32 into LDS by
-//     one 4-byte load per variable.
+//     loads (the LDS stays small enough not to limit the waves per SIMD --
+//     measured faster than loading it into LDS), FP32 into LDS by one 4-byte
+//     load per variable.
 // The directions are then processed one after the other, each followed by
 // the interface correction of the lanes on its faces (own flux still in
-// registers).  Along x and y the flux is staged in LDS and swept with D
-// (scaled by -2/h_l).  Along z the contraction is one FP64 matrix-core
-// instruction per variable: the 4-block 4x4x4 MFMA multiplies, in block b,
-// A[i][k] held by lane i + 4b + 16k with B[k][n] held by lane n + 4b + 16k
-// and accumulates into C[i][n] held by lane n + 4b + 16i.  With node index
-// x + 4y + 16z on the lane, B = the lane's own flux (k = z, n = x, b = y),
-// A = the scaled D entry D[i][k] of lane i + 4b + 16k, and C = the lane's own
-// accumulator (i = z): the z sweep needs no data movement at all, which
-// takes a third of the sweep's LDS traffic and FMAs off the shared LDS and
-// vector pipes.  Being one wave, the workgroup needs no barrier: LDS
-// accesses of a wave complete in order, and a wave-level fence keeps the
-// compiler from reordering them.
+// registers).  In FP64 the derivative sweeps run on the matrix core: the
+// 4-block 4x4x4 MFMA multiplies, in block b, A[i][k] held by lane
+// i + 4b + 16k with B[k][n] held by lane n + 4b + 16k and accumulates into
+// C[i][n] held by lane n + 4b + 16i, i.e. it contracts over lane bits 4-5 and
+// returns the result in those bits.  The node index is x + 4y + 16z on the
+// lane, so
+//   * along z the lane's own flux is the B operand, the scaled D entry
+//     D[i][k] of lane i + 4b + 16k the A operand, the lane's own accumulator
+//     the C operand: no data movement at all;
+//   * along x (y) the flux is staged in LDS and lane L reads as B operand the
+//     flux of node T(L) (S(L)), T swapping lane bits 0-1 with 4-5 (S: 2-3
+//     with 4-5), so that the contraction index sits in bits 4-5; lane L then
+//     holds the result of node T(L) (S(L)), and as T and S are their own
+//     inverses each lane fetches its node's result from lane T(L) (S(L)) by
+//     a lane permute (ds_bpermute, two 32-bit moves per double).
+// Per direction that is 5 matrix instructions and 7.5 KB of LDS traffic per
+// wave instead of 20 FMAs and 14.5 KB (a staged flux swept with D read from
+// LDS).  Being one wave, the workgroup needs no barrier: LDS accesses of a
+// wave complete in order, and a wave-level fence keeps the compiler from
+// reordering them.
 //
-// FP32 form: fluxes and face corrections in double, the x and y fluxes
-// staged as float differences from the element's first-node flux (D
+// FP32 form: the state, U0, the output and the neighbour face nodes in LDS
+// are float, fluxes and face corrections double.  Along x and y it stages
+// each flux as the float difference from the element's first-node flux (D
 // annihilates constants, so the sum is unchanged and the rounding error is
-// relative to the variation inside the element), float sweeps and
-// accumulator; the z contraction in double on the matrix core, rounded once
-// into the accumulator.
+// relative to the variation inside the element) and sweeps it in float from
+// LDS into a float accumulator; the z contraction runs on the matrix core in
+// double and is rounded once into that accumulator.  The FP32 form is bound
+// by vector instruction issue at cache-resident sizes, and the FP64 matrix
+// instruction occupies the SIMD about as long as the FMAs it replaces, so
+// there the double x/y matrix path (staged double flux, permutes) measured
+// slower than the float sweep.
 //
 // The interface correction of a lane on the s face of direction l
 // (s = +1 on the +xi_l face, -1 on the -xi_l face) is the Rusanov
@@ -423,6 +436,15 @@ __device__ __forceinline__ double lane0(double x) {
   return __builtin_bit_cast(double, r);
 }
 
+// x of lane src (src = lane index), for a double
+__device__ __forceinline__ double lane_fetch(int src, double x) {
+  const u32x2 w = __builtin_bit_cast(u32x2, x);
+  u32x2 r;
+  r.x = (unsigned)__builtin_amdgcn_ds_bpermute(src * 4, (int)w.x);
+  r.y = (unsigned)__builtin_amdgcn_ds_bpermute(src * 4, (int)w.y);
+  return __builtin_bit_cast(double, r);
+}
+
 template <typename T, bool NT>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
 k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
@@ -432,14 +454,13 @@ k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
   constexpr int CP = NT ? CPOL_NT : 0;  // policy of the streams no other workgroup reads: U0 and the output
   constexpr int WPV = F32 ? 32 : 64;  // dwords of face data per direction and variable
   __shared__ T sF[NV][NP];
-  __shared__ T sDg[2][n * n];
+  __shared__ float sDg[F32 ? 2 : 1][F32 ? n * n : 1];  // FP32: D scaled by -2/h_l for x and y
   __shared__ __attribute__((aligned(16))) unsigned sNb[DIM][NV][WPV];
   __shared__ __attribute__((aligned(16))) T sU0[F32 ? NV : 1][F32 ? NP : 1];
 
   const int tid = threadIdx.x;
-  const double dsc = tid < n * n ? mv.K->D[tid] : 0.0;
-  // matrix-core operand of the z sweep: D[i][k] on lane i + 4b + 16k
-  const double dz = mv.K->D[(tid & 3) * n + (tid >> 4)];
+  // matrix-core A operand: D[i][k] on lane i + 4b + 16k
+  const double dA = mv.K->D[(tid & 3) * n + (tid >> 4)];
   const int E = mv.E;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int b = blk / E;
@@ -506,11 +527,16 @@ k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
 #pragma unroll
   for (int d = 0; d < DIM; ++d) vel[d] = u[1 + d] * th.ri;
   const double aown = wave_sound<PHYS, F32>(th);
-  if (tid < n * n) {
+  if constexpr (F32) {
+    if (tid < n * n) {
+      const double dsc = mv.K->D[tid];
 #pragma unroll
-    for (int l = 0; l < 2; ++l) sDg[l][tid] = static_cast<T>(-g[l] * dsc);
+      for (int l = 0; l < 2; ++l) sDg[l][tid] = static_cast<float>(-g[l] * dsc);
+    }
   }
-  const double az = -g[2] * dz;
+  // nodes whose flux this lane holds as B operand along x and y
+  const int tx = (tid >> 4) | (tid & 12) | ((tid & 3) << 4);
+  const int ty = (tid & 3) | ((tid >> 4) << 2) | (((tid >> 2) & 3) << 4);
   // byte offset of this lane's slot in sNb[l][v] for each direction l, one
   // byte per direction (meaningful on the lanes of an l face, whose face
   // side is the low bit of their index along l):
@@ -529,29 +555,35 @@ k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
     const int il = ii[l];
     double F[NV];
     PHYS::flux(u, vel[l], th.p, l, F);
+    const double al = -g[l] * dA;  // D scaled by -2/h_l
     if (l < 2) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        // FP32: relative to the element's first node (D annihilates constants)
         if constexpr (F32) sF[v][tid] = static_cast<float>(F[v] - lane0(F[v]));
         else sF[v][tid] = F[v];
       }
       wave_lds_fence();
-      // volume integral along l
-      const int st = stride[l], base = tid - il * st;
-      T drow[n];
+      if constexpr (F32) {
+        const int st = stride[l], base = tid - il * st;
+        float drow[n];
 #pragma unroll
-      for (int m = 0; m < n; ++m) drow[m] = sDg[l][il * n + m];
+        for (int m = 0; m < n; ++m) drow[m] = sDg[l][il * n + m];
 #pragma unroll
-      for (int v = 0; v < NV; ++v)
+        for (int v = 0; v < NV; ++v)
 #pragma unroll
-        for (int m = 0; m < n; ++m) acc[v] = fma(drow[m], sF[v][base + m * st], acc[v]);
+          for (int m = 0; m < n; ++m) acc[v] = fma(drow[m], sF[v][base + m * st], acc[v]);
+      } else {
+        const int src = l == 0 ? tx : ty;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          acc[v] += lane_fetch(src, __builtin_amdgcn_mfma_f64_4x4x4f64(al, sF[v][src], 0.0, 0, 0, 0));
+      }
+      wave_lds_fence();  // the next direction overwrites sF
     } else {
-      // volume integral along z on the matrix core
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        if constexpr (F32) acc[v] += static_cast<float>(__builtin_amdgcn_mfma_f64_4x4x4f64(az, F[v], 0.0, 0, 0, 0));
-        else acc[v] = __builtin_amdgcn_mfma_f64_4x4x4f64(az, F[v], acc[v], 0, 0, 0);
+        if constexpr (F32) acc[v] += static_cast<float>(__builtin_amdgcn_mfma_f64_4x4x4f64(al, F[v], 0.0, 0, 0, 0));
+        else acc[v] = __builtin_amdgcn_mfma_f64_4x4x4f64(al, F[v], acc[v], 0, 0, 0);
       }
     }
     // interface correction on the l faces
@@ -579,7 +611,6 @@ k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
         else acc[v] = fma(cs, Fn[v] - F[v], fma(cl, un[v] - u[v], acc[v]));
       }
     }
-    if (l < 2) wave_lds_fence();  // the next direction overwrites sF
   }
 
   // ---- output ----------------------------------------------------------------
