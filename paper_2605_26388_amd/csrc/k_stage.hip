@@ -410,16 +410,15 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
 // reordering them.
 //
 // FP32 form: the state, U0, the output and the neighbour face nodes in LDS
-// are float, fluxes and face corrections double.  Along x and y it stages
-// each flux as the float difference from the element's first-node flux (D
-// annihilates constants, so the sum is unchanged and the rounding error is
-// relative to the variation inside the element) and sweeps it in float from
-// LDS into a float accumulator; the z contraction runs on the matrix core in
-// double and is rounded once into that accumulator.  The FP32 form is bound
-// by vector instruction issue at cache-resident sizes, and the FP64 matrix
-// instruction occupies the SIMD about as long as the FMAs it replaces, so
-// there the double x/y matrix path (staged double flux, permutes) measured
-// slower than the float sweep.
+// are float, fluxes and face corrections double.  In every direction it
+// stages the flux as the float difference from the element's first-node
+// flux (D annihilates constants, so the sum is unchanged and the rounding
+// error is relative to the variation inside the element) and sweeps it in
+// float from LDS into a float accumulator.  It is bound by vector
+// instruction issue at cache-resident sizes, and the FP64 matrix instruction
+// occupies the SIMD about as long as the FMAs it replaces: a double matrix
+// path measured slower there (and, needing more registers, one wave per
+// SIMD fewer, also past the Infinity Cache).
 //
 // The interface correction of a lane on the s face of direction l
 // (s = +1 on the +xi_l face, -1 on the -xi_l face) is the Rusanov
@@ -454,13 +453,15 @@ k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
   constexpr int CP = NT ? CPOL_NT : 0;  // policy of the streams no other workgroup reads: U0 and the output
   constexpr int WPV = F32 ? 32 : 64;  // dwords of face data per direction and variable
   __shared__ T sF[NV][NP];
-  __shared__ float sDg[F32 ? 2 : 1][F32 ? n * n : 1];  // FP32: D scaled by -2/h_l for x and y
+  __shared__ float sDg[F32 ? DIM : 1][F32 ? n * n : 1];  // FP32: D scaled by -2/h_l
   __shared__ __attribute__((aligned(16))) unsigned sNb[DIM][NV][WPV];
   __shared__ __attribute__((aligned(16))) T sU0[F32 ? NV : 1][F32 ? NP : 1];
 
   const int tid = threadIdx.x;
   // matrix-core A operand: D[i][k] on lane i + 4b + 16k
-  const double dA = mv.K->D[(tid & 3) * n + (tid >> 4)];
+  // D[tid] for the FP32 form's tables of scaled rows (lanes < 16)
+  const double dsc = (F32 && tid < n * n) ? mv.K->D[tid] : 0.0;
+  const double dA = F32 ? 0.0 : mv.K->D[(tid & 3) * n + (tid >> 4)];
   const int E = mv.E;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int b = blk / E;
@@ -529,9 +530,8 @@ k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
   const double aown = wave_sound<PHYS, F32>(th);
   if constexpr (F32) {
     if (tid < n * n) {
-      const double dsc = mv.K->D[tid];
 #pragma unroll
-      for (int l = 0; l < 2; ++l) sDg[l][tid] = static_cast<float>(-g[l] * dsc);
+      for (int l = 0; l < DIM; ++l) sDg[l][tid] = static_cast<float>(-g[l] * dsc);
     }
   }
   // nodes whose flux this lane holds as B operand along x and y
@@ -555,60 +555,77 @@ k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
     const int il = ii[l];
     double F[NV];
     PHYS::flux(u, vel[l], th.p, l, F);
-    const double al = -g[l] * dA;  // D scaled by -2/h_l
-    if (l < 2) {
+    if constexpr (F32) {
+      // float sweep of the staged flux difference from LDS
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        if constexpr (F32) sF[v][tid] = static_cast<float>(F[v] - lane0(F[v]));
-        else sF[v][tid] = F[v];
-      }
+      for (int v = 0; v < NV; ++v) sF[v][tid] = static_cast<float>(F[v] - lane0(F[v]));
       wave_lds_fence();
-      if constexpr (F32) {
-        const int st = stride[l], base = tid - il * st;
-        float drow[n];
+      const int st = stride[l], base = tid - il * st;
+      float drow[n];
 #pragma unroll
-        for (int m = 0; m < n; ++m) drow[m] = sDg[l][il * n + m];
+      for (int m = 0; m < n; ++m) drow[m] = sDg[l][il * n + m];
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
+      for (int v = 0; v < NV; ++v)
 #pragma unroll
-          for (int m = 0; m < n; ++m) acc[v] = fma(drow[m], sF[v][base + m * st], acc[v]);
-      } else {
+        for (int m = 0; m < n; ++m) acc[v] = fma(drow[m], sF[v][base + m * st], acc[v]);
+      // interface correction on the l faces: 2 (F* - F_own) = (F_nb - F_own) - s lam (U_nb - U_own),
+      // added times -s (2/h_l) / (2 w_end)
+      const int side = (il == 0) ? 0 : ((il == N) ? 1 : -1);
+      if (side >= 0) {
+        const int o1 = l == 0 ? 1 : 0, o2 = l == 2 ? 1 : 2;
+        const int slot = side * 16 + ii[o1] + 4 * ii[o2];
+        double un[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) un[v] = static_cast<double>(__builtin_bit_cast(float, sNb[l][v][slot]));
+        Thermo tn;
+        PHYS::thermo(un, tn, pc);
+        const double vn = un[1 + l] * tn.ri;
+        double Fn[NV];
+        PHYS::flux(un, vn, tn.p, l, Fn);
+        const double lam = fmax(fabs(vel[l]) + aown, fabs(vn) + wave_sound<PHYS, F32>(tn));
+        const double sgn = side == 1 ? 1.0 : -1.0;
+        const double hs = sgn * lam;
+        const double sc = -sgn * (g[l] * hwinv);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const double dv = fma(-hs, un[v] - u[v], Fn[v] - F[v]);
+          acc[v] = fma(static_cast<float>(sc), static_cast<float>(dv), acc[v]);
+        }
+      }
+      wave_lds_fence();  // the next direction overwrites sF
+    } else {
+      const double al = -g[l] * dA;  // D scaled by -2/h_l
+      if (l < 2) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sF[v][tid] = F[v];
+        wave_lds_fence();
         const int src = l == 0 ? tx : ty;
 #pragma unroll
         for (int v = 0; v < NV; ++v)
           acc[v] += lane_fetch(src, __builtin_amdgcn_mfma_f64_4x4x4f64(al, sF[v][src], 0.0, 0, 0, 0));
-      }
-      wave_lds_fence();  // the next direction overwrites sF
-    } else {
+        wave_lds_fence();  // the next direction overwrites sF
+      } else {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        if constexpr (F32) acc[v] += static_cast<float>(__builtin_amdgcn_mfma_f64_4x4x4f64(al, F[v], 0.0, 0, 0, 0));
-        else acc[v] = __builtin_amdgcn_mfma_f64_4x4x4f64(al, F[v], acc[v], 0, 0, 0);
+        for (int v = 0; v < NV; ++v) acc[v] = __builtin_amdgcn_mfma_f64_4x4x4f64(al, F[v], acc[v], 0, 0, 0);
       }
-    }
-    // interface correction on the l faces
-    if (il == 0 || il == N) {
-      const unsigned so = (fslots >> (8 * l)) & 0xffu;
-      double un[NV];
+      // interface correction on the l faces
+      if (il == 0 || il == N) {
+        const unsigned so = (fslots >> (8 * l)) & 0xffu;
+        double un[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const char* p = reinterpret_cast<const char*>(&sNb[l][v][0]) + so;
-        if constexpr (F32) un[v] = static_cast<double>(*reinterpret_cast<const float*>(p));
-        else un[v] = *reinterpret_cast<const double*>(p);
-      }
-      Thermo tn;
-      PHYS::thermo(un, tn, pc);
-      const double vn = un[1 + l] * tn.ri;
-      double Fn[NV];
-      PHYS::flux(un, vn, tn.p, l, Fn);
-      const double lam = fmax(fabs(vel[l]) + aown, fabs(vn) + wave_sound<PHYS, F32>(tn));
-      const double c = g[l] * hwinv;
-      const double cl = c * lam;
-      const double cs = (il == N) ? -c : c;
+        for (int v = 0; v < NV; ++v)
+          un[v] = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(&sNb[l][v][0]) + so);
+        Thermo tn;
+        PHYS::thermo(un, tn, pc);
+        const double vn = un[1 + l] * tn.ri;
+        double Fn[NV];
+        PHYS::flux(un, vn, tn.p, l, Fn);
+        const double lam = fmax(fabs(vel[l]) + aown, fabs(vn) + wave_sound<PHYS, F32>(tn));
+        const double c = g[l] * hwinv;
+        const double cl = c * lam;
+        const double cs = (il == N) ? -c : c;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        if constexpr (F32) acc[v] += static_cast<float>(fma(cs, Fn[v] - F[v], cl * (un[v] - u[v])));
-        else acc[v] = fma(cs, Fn[v] - F[v], fma(cl, un[v] - u[v], acc[v]));
+        for (int v = 0; v < NV; ++v) acc[v] = fma(cs, Fn[v] - F[v], fma(cl, un[v] - u[v], acc[v]));
       }
     }
   }
