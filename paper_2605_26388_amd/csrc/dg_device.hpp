@@ -149,6 +149,16 @@ __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The value x of lane src (a lane index of the wave), for a double: two
+// 32-bit lane permutes (ds_bpermute, on the LDS crossbar; no LDS memory).
+__device__ __forceinline__ double lane_fetch(int src, double x) {
+  const unsigned lo = (unsigned)__builtin_bit_cast(unsigned long long, x);
+  const unsigned hi = (unsigned)(__builtin_bit_cast(unsigned long long, x) >> 32);
+  const unsigned rlo = (unsigned)__builtin_amdgcn_ds_bpermute(src * 4, (int)lo);
+  const unsigned rhi = (unsigned)__builtin_amdgcn_ds_bpermute(src * 4, (int)hi);
+  return __builtin_bit_cast(double, ((unsigned long long)rhi << 32) | rlo);
+}
+
 // an LDS address for the buffer-to-LDS load builtin
 #define DG_LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
 

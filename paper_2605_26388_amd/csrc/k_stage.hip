@@ -435,15 +435,6 @@ __device__ __forceinline__ double lane0(double x) {
   return __builtin_bit_cast(double, r);
 }
 
-// x of lane src (src = lane index), for a double
-__device__ __forceinline__ double lane_fetch(int src, double x) {
-  const u32x2 w = __builtin_bit_cast(u32x2, x);
-  u32x2 r;
-  r.x = (unsigned)__builtin_amdgcn_ds_bpermute(src * 4, (int)w.x);
-  r.y = (unsigned)__builtin_amdgcn_ds_bpermute(src * 4, (int)w.y);
-  return __builtin_bit_cast(double, r);
-}
-
 template <typename T, bool NT>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
 k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
