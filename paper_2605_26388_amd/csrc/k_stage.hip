@@ -382,10 +382,9 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
 //     slot L >> 1, in FP32 lane L < 32 fetches slot L (slots 0-15 the -xi_l
 //     face, 16-31 the +xi_l face, tangential index a + 4 b in the two other
 //     directions);
-//   * U0, when the stage reads it: FP64 into registers right after those
-//     loads (the LDS stays small enough not to limit the waves per SIMD --
-//     measured faster than loading it into LDS), FP32 into LDS by one 4-byte
-//     load per variable.
+//   * U0, when the stage reads it, into LDS by buffer-to-LDS loads as well
+//     (FP64: two 4-byte loads per lane and variable, FP32: one), read only
+//     by the output.
 // The directions are then processed one after the other, each followed by
 // the interface correction of the lanes on its faces (own flux still in
 // registers).  In FP64 the derivative sweeps run on the matrix core: the
@@ -397,16 +396,19 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
 //   * along z the lane's own flux is the B operand, the scaled D entry
 //     D[i][k] of lane i + 4b + 16k the A operand, the lane's own accumulator
 //     the C operand: no data movement at all;
-//   * along x (y) the flux is staged in LDS and lane L reads as B operand the
-//     flux of node T(L) (S(L)), T swapping lane bits 0-1 with 4-5 (S: 2-3
-//     with 4-5), so that the contraction index sits in bits 4-5; lane L then
-//     holds the result of node T(L) (S(L)), and as T and S are their own
-//     inverses each lane fetches its node's result from lane T(L) (S(L)) by
-//     a lane permute (ds_bpermute, two 32-bit moves per double).
-// Per direction that is 5 matrix instructions and 7.5 KB of LDS traffic per
-// wave instead of 20 FMAs and 14.5 KB (a staged flux swept with D read from
-// LDS).  Being one wave, the workgroup needs no barrier: LDS accesses of a
-// wave complete in order, and a wave-level fence keeps the compiler from
+//   * along x (y) lane L takes as B operand the flux of node T(L) (S(L)),
+//     T swapping lane bits 0-1 with 4-5 (S: 2-3 with 4-5), so that the
+//     contraction index sits in bits 4-5; lane L then holds the result of
+//     node T(L) (S(L)).  T and S are their own inverses, so both moves are a
+//     fetch from lane T(L) (S(L)) by a lane permute (ds_bpermute, two 32-bit
+//     moves per double): the operand before the product, the result after.
+// Per direction that is 5 matrix instructions and 5 KB of permute traffic
+// per wave instead of 20 FMAs and 14.5 KB of LDS traffic (a staged flux swept
+// with D read from LDS), and no LDS tile for the flux: with U0 in LDS
+// instead of ten registers the FP64 kernel holds 76 VGPRs and runs 6 waves
+// per SIMD (86 VGPRs and 5 waves with U0 in registers and a staged flux).
+// Being one wave, the workgroup needs no barrier: LDS accesses of a wave
+// complete in order, and a wave-level fence keeps the compiler from
 // reordering them.
 //
 // FP32 form: the state, U0, the output and the neighbour face nodes in LDS
@@ -443,10 +445,10 @@ k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
   constexpr bool F32 = std::is_same<T, float>::value;
   constexpr int CP = NT ? CPOL_NT : 0;  // policy of the streams no other workgroup reads: U0 and the output
   constexpr int WPV = F32 ? 32 : 64;  // dwords of face data per direction and variable
-  __shared__ T sF[NV][NP];
+  __shared__ T sF[F32 ? NV : 1][F32 ? NP : 1];  // FP32: the staged flux of the float sweeps
   __shared__ float sDg[F32 ? DIM : 1][F32 ? n * n : 1];  // FP32: D scaled by -2/h_l
   __shared__ __attribute__((aligned(16))) unsigned sNb[DIM][NV][WPV];
-  __shared__ __attribute__((aligned(16))) T sU0[F32 ? NV : 1][F32 ? NP : 1];
+  __shared__ __attribute__((aligned(16))) T sU0[NV][NP];
 
   const int tid = threadIdx.x;
   // matrix-core A operand: D[i][k] on lane i + 4b + 16k
@@ -499,17 +501,19 @@ k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
     }
   }
   const bool use_u0 = (sp.mode != 0) && (sp.a != 0.0);
-  double u0r[NV];  // FP64: U0 in registers
-  if (!F32 && use_u0) {
+  if (use_u0) {  // U0 into LDS, one 4-byte load per lane and dword
     const rsrc_t r0 = make_rsrc(static_cast<const T*>(sp.U0) + (size_t)b * NV * plane, abytes);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) u0r[v] = Buf<T>::template load<CP>(r0, off, v * pstride);
-  }
-  if (F32 && use_u0) {  // FP32: U0 into LDS
-    const rsrc_t r0 = make_rsrc(static_cast<const T*>(sp.U0) + (size_t)b * NV * plane, abytes);
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(r0, DG_LDS_PTR(&sU0[v][0]), 4, off * 4u, v * pstride, 0, CP);
+    for (int v = 0; v < NV; ++v) {
+      if constexpr (F32) {
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r0, DG_LDS_PTR(&sU0[v][0]), 4, off * 4u, v * pstride, 0, CP);
+      } else {
+        // lane L fetches dword L of the element's 512-byte plane, then dword 64 + L
+        const unsigned o = (unsigned)(ec * NP) * 8u + 4u * (unsigned)tid;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r0, DG_LDS_PTR(&sU0[v][0]), 4, o, v * pstride, 0, CP);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r0, DG_LDS_PTR(&sU0[v][32]), 4, o + 256u, v * pstride, 0, CP);
+      }
+    }
   }
 
   Thermo th;
@@ -587,14 +591,10 @@ k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
     } else {
       const double al = -g[l] * dA;  // D scaled by -2/h_l
       if (l < 2) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) sF[v][tid] = F[v];
-        wave_lds_fence();
         const int src = l == 0 ? tx : ty;
 #pragma unroll
         for (int v = 0; v < NV; ++v)
-          acc[v] += lane_fetch(src, __builtin_amdgcn_mfma_f64_4x4x4f64(al, sF[v][src], 0.0, 0, 0, 0));
-        wave_lds_fence();  // the next direction overwrites sF
+          acc[v] += lane_fetch(src, __builtin_amdgcn_mfma_f64_4x4x4f64(al, lane_fetch(src, F[v]), 0.0, 0, 0, 0));
       } else {
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[v] = __builtin_amdgcn_mfma_f64_4x4x4f64(al, F[v], acc[v], 0, 0, 0);
@@ -632,7 +632,7 @@ k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     r[v] = fma(T(sp.c), acc[v], T(sp.b) * T(u[v]));
-    if (use_u0) r[v] = fma(T(sp.a), F32 ? sU0[v][tid] : T(u0r[v]), r[v]);
+    if (use_u0) r[v] = fma(T(sp.a), sU0[v][tid], r[v]);
   }
   if (sp.rho_min > 0.0 || sp.p_min > 0.0) {  // the floor itself in double
     if constexpr (F32) {
