@@ -60,6 +60,11 @@ k_stage_curv(StageParams sp, MeshView mv, PhysConst pc, CurvArgs ca) {
   const int tid = threadIdx.x;
   static_assert(n * n <= S::BS, "one D entry per lane");
   const double dval = tid < n * n ? mv.K->D[tid] : 0.0;
+  // 3-D, N = 3 (one element per wave): the standard volume sweep runs on the
+  // FP64 matrix core as in the Cartesian stage kernel, whose header describes
+  // the lane layout; A operand -D[i][k] on lane i + 4b + 16k
+  constexpr bool MMA = (DIM == 3 && N == 3 && !SPLIT);
+  const double dA = MMA ? -mv.K->D[(tid & 3) * n + (tid >> 4)] : 0.0;
 
   const int E = mv.E;
   const int nEB = (E + EPB - 1) / EPB;
@@ -175,6 +180,18 @@ k_stage_curv(StageParams sp, MeshView mv, PhysConst pc, CurvArgs ca) {
         for (int v = 0; v < NV; ++v) acc[v] = 0.0;
         split_sweep_curv<DIM, N, 0, true>(tid, ii, stride, own, sQ, sJ, Ja, sD, gm1i, far, acc);
       }
+    }
+  } else if constexpr (MMA) {
+    // z: the lane's own flux is the B operand; x (y): the flux of the node
+    // whose lane bits 0-1 (2-3) and 4-5 are swapped, the result fetched back
+    // from that lane (both swaps are their own inverse)
+    const int tx = (tid >> 4) | (tid & 12) | ((tid & 3) << 4);
+    const int ty = (tid & 3) | ((tid >> 4) << 2) | (((tid >> 2) & 3) << 4);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      acc[v] = __builtin_amdgcn_mfma_f64_4x4x4f64(dA, sF[2][v][tid], acc[v], 0, 0, 0);
+      acc[v] += lane_fetch(tx, __builtin_amdgcn_mfma_f64_4x4x4f64(dA, sF[0][v][tx], 0.0, 0, 0, 0));
+      acc[v] += lane_fetch(ty, __builtin_amdgcn_mfma_f64_4x4x4f64(dA, sF[1][v][ty], 0.0, 0, 0, 0));
     }
   } else if (tid < S::NT) {
 #pragma unroll
