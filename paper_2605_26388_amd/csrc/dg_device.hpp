@@ -159,6 +159,14 @@ __device__ __forceinline__ double lane_fetch(int src, double x) {
   return __builtin_bit_cast(double, ((unsigned long long)rhi << 32) | rlo);
 }
 
+// Wait until every vector-memory load of the wave has completed.  Data that
+// buffer-to-LDS loads write is read with plain LDS loads; the compiler's own
+// wait before such a read has been found to count only part of the
+// outstanding buffer-to-LDS loads when more than a few are in flight, so the
+// kernels that use them wait for all loads explicitly before their first
+// read of that data.
+__device__ __forceinline__ void wait_vmem_all() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 // an LDS address for the buffer-to-LDS load builtin
 #define DG_LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
 

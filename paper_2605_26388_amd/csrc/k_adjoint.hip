@@ -355,6 +355,9 @@ __global__ void __launch_bounds__(64) k_adjoint_n3(AdjParams ap, MeshView mv, Ph
   double gout[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) gout[v] = 0.0;
+  // the neighbour face nodes of U_k and lambda_out (and FP32 lambda_0) arrive
+  // in LDS by buffer-to-LDS loads
+  wait_vmem_all();
 #pragma unroll
   for (int l = 0; l < DIM; ++l) {
     const int il = ii[l], st = stride[l];

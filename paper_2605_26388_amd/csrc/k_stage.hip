@@ -437,8 +437,11 @@ __device__ __forceinline__ double lane0(double x) {
   return __builtin_bit_cast(double, r);
 }
 
-template <typename T, bool NT>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
+// U0: whether the stage reads U0 (a != 0 in a Shu-Osher stage); without it
+// the FP64 kernel needs 3.8 KB of LDS and 72 VGPRs and runs 7 waves per SIMD
+// instead of 6.
+template <typename T, bool NT, bool U0>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((!std::is_same<T, float>::value && !U0) ? 7 : 4)))
 k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
   using PHYS = EulerPhys<3>;
   constexpr int DIM = 3, N = 3, n = 4, NP = 64, NV = 5;
@@ -448,7 +451,7 @@ k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
   __shared__ T sF[F32 ? NV : 1][F32 ? NP : 1];  // FP32: the staged flux of the float sweeps
   __shared__ float sDg[F32 ? DIM : 1][F32 ? n * n : 1];  // FP32: D scaled by -2/h_l
   __shared__ __attribute__((aligned(16))) unsigned sNb[DIM][NV][WPV];
-  __shared__ __attribute__((aligned(16))) T sU0[NV][NP];
+  __shared__ __attribute__((aligned(16))) T sU0[U0 ? NV : 1][U0 ? NP : 1];
 
   const int tid = threadIdx.x;
   // matrix-core A operand: D[i][k] on lane i + 4b + 16k
@@ -500,8 +503,8 @@ k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
       }
     }
   }
-  const bool use_u0 = (sp.mode != 0) && (sp.a != 0.0);
-  if (use_u0) {  // U0 into LDS, one 4-byte load per lane and dword
+  constexpr bool use_u0 = U0;  // the host launches this instantiation iff mode != 0 and a != 0
+  if constexpr (use_u0) {  // U0 into LDS, one 4-byte load per lane and dword
     const rsrc_t r0 = make_rsrc(static_cast<const T*>(sp.U0) + (size_t)b * NV * plane, abytes);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -564,7 +567,9 @@ k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
 #pragma unroll
         for (int m = 0; m < n; ++m) acc[v] = fma(drow[m], sF[v][base + m * st], acc[v]);
       // interface correction on the l faces: 2 (F* - F_own) = (F_nb - F_own) - s lam (U_nb - U_own),
-      // added times -s (2/h_l) / (2 w_end)
+      // added times -s (2/h_l) / (2 w_end); the neighbour face nodes (and U0)
+      // arrive in LDS by buffer-to-LDS loads
+      if (l == 0) wait_vmem_all();
       const int side = (il == 0) ? 0 : ((il == N) ? 1 : -1);
       if (side >= 0) {
         const int o1 = l == 0 ? 1 : 0, o2 = l == 2 ? 1 : 2;
@@ -599,7 +604,9 @@ k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[v] = __builtin_amdgcn_mfma_f64_4x4x4f64(al, F[v], acc[v], 0, 0, 0);
       }
-      // interface correction on the l faces
+      // interface correction on the l faces; the neighbour face nodes (and
+      // U0) arrive in LDS by buffer-to-LDS loads
+      if (l == 0) wait_vmem_all();
       if (il == 0 || il == N) {
         const unsigned so = (fslots >> (8 * l)) & 0xffu;
         double un[NV];
@@ -632,7 +639,7 @@ k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     r[v] = fma(T(sp.c), acc[v], T(sp.b) * T(u[v]));
-    if (use_u0) r[v] = fma(T(sp.a), sU0[v][tid], r[v]);
+    if constexpr (use_u0) r[v] = fma(T(sp.a), sU0[v][tid], r[v]);
   }
   if (sp.rho_min > 0.0 || sp.p_min > 0.0) {  // the floor itself in double
     if constexpr (F32) {
@@ -742,10 +749,13 @@ static hipError_t go(const Ctx& c, const StageParams& sp, hipStream_t s) {
     // displacing the neighbour faces in L2 (at cache-resident sizes it would
     // send the output past the cache the next stage reads it from)
     const size_t state_bytes = (size_t)c.B * 5 * c.E * 64 * sizeof(T);
-    if (state_bytes > NT_STATE_BYTES)
-      hipLaunchKernelGGL((k_stage_n3<T, true>), dim3(nblk), dim3(64), 0, s, sp, mesh_view(c), c.pc);
-    else
-      hipLaunchKernelGGL((k_stage_n3<T, false>), dim3(nblk), dim3(64), 0, s, sp, mesh_view(c), c.pc);
+    const bool nt = state_bytes > NT_STATE_BYTES;
+    const bool u0 = sp.mode != 0 && sp.a != 0.0;
+    const MeshView mvw = mesh_view(c);
+    if (nt && u0) hipLaunchKernelGGL((k_stage_n3<T, true, true>), dim3(nblk), dim3(64), 0, s, sp, mvw, c.pc);
+    else if (nt) hipLaunchKernelGGL((k_stage_n3<T, true, false>), dim3(nblk), dim3(64), 0, s, sp, mvw, c.pc);
+    else if (u0) hipLaunchKernelGGL((k_stage_n3<T, false, true>), dim3(nblk), dim3(64), 0, s, sp, mvw, c.pc);
+    else hipLaunchKernelGGL((k_stage_n3<T, false, false>), dim3(nblk), dim3(64), 0, s, sp, mvw, c.pc);
     return hipGetLastError();
   }
   hipLaunchKernelGGL((k_stage<DIM, N, PHYS, T, MORTAR, SPLIT>), dim3(nblk), dim3(SH::BS), 0, s, sp, mesh_view(c),
