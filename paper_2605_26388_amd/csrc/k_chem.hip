@@ -25,7 +25,7 @@
 //   of the state.  The substep runs in two passes: the first makes every
 //   node's Newton iteration at h and hands the nodes that need the
 //   continuation (a node index and its iteration count) to the second, which
-//   runs each of them on a group of eight lanes (k_source_cont below).
+//   runs each of them on a group of 32 lanes (k_source_cont below).
 #include <algorithm>
 
 #include "dg_device.hpp"
@@ -83,6 +83,33 @@ struct Chem {
         if (dnu != 0) w[s] = fma(m->kappa_r * m->W[s] * dnu, Rr, w[s]);
       }
     }
+  }
+
+  // net rate of reaction r alone, M_r (k_f prod X^nu' - k_b prod X^nu''), with
+  // wdot's arithmetic term for term (wdot adds kappa_r W_s dnu_rs times it to
+  // each species in the order r = 0, 1, ...)
+  __device__ __forceinline__ double rate(int r, const double (&Y)[NS], double T) const {
+    double X[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) X[s] = m->kappa_c * Y[s] / m->W[s];
+    const double lnT = log(T);
+    const double Ti = 1.0 / T;
+    double fwd = m->A_f[r] * exp(fma(m->beta_f[r], lnT, -m->theta_f[r] * Ti));
+    double bwd = 0.0;
+    for (int s = 0; s < NS; ++s)
+      for (int q = 0; q < m->nu_f[r][s]; ++q) fwd *= X[s];
+    if (m->reversible[r]) {
+      bwd = m->A_b[r] * exp(fma(m->beta_b[r], lnT, -m->theta_b[r] * Ti));
+      for (int s = 0; s < NS; ++s)
+        for (int q = 0; q < m->nu_b[r][s]; ++q) bwd *= X[s];
+    }
+    double M = 1.0;
+    if (m->third_body[r]) {
+      M = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) M = fma(m->eff[r][s], X[s], M);
+    }
+    return M * (fwd - bwd);
   }
 
   // R(Y) = Y - Yn - h wdot(Y, T(Y)); returns T(Y)
@@ -280,13 +307,17 @@ k_source(const T* U, T* out, const dg_mechanism* mech, size_t plane, int B, doub
 
 // ---------------------------------------------------------------------------
 // Second pass of the implicit substep: the continuation in h of the nodes the
-// first pass handed over, one node per group of G = 8 lanes.  In each Newton
-// iteration the six residual evaluations (the base point on lane NS, the
-// point displaced along Y_k on lane k) run side by side and are exchanged by
-// lane shuffles; every lane of the group then forms the same difference
-// Jacobian and solves the same system, so the iterates are those of the
-// one-lane iteration bit for bit, while an iteration takes about one
-// evaluation's latency instead of six.  The few nodes that need the
+// first pass handed over, one node per group of G = 32 lanes.  In each Newton
+// iteration the six residual evaluations (the base point, the point displaced
+// along Y_k for each k) run side by side, each spread over NR lanes, one per
+// reaction: lane p NR + r evaluates reaction r's two Arrhenius rates at point
+// p (p = NS the base point; lanes past NS NR + NR - 1 repeat the base point),
+// the point's NR rates are gathered by lane shuffles and summed into the
+// species rates in the order r = 0, 1, .. of the one-lane evaluation.  Every
+// lane of the group then forms the same difference Jacobian and solves the
+// same system, so the iterates are those of the one-lane iteration bit for
+// bit, while an iteration takes about one reaction's latency (two
+// exponentials) instead of six evaluations of NR reactions each.  The few nodes that need the
 // continuation (a few per cent at the surveyed stiffness, up to 40 levels of
 // Newton solves) otherwise keep their whole wave waiting.
 // ---------------------------------------------------------------------------
@@ -294,10 +325,13 @@ template <typename T, int NS, int NR, int DIM>
 __global__ void __launch_bounds__(256)
 k_source_cont(const T* U, T* out, const dg_mechanism* mech, size_t plane, double h, int max_iter, double tol,
               int* counters, unsigned long long* first_bad, const DeferredNode* defer, const int* defer_count) {
-  constexpr int G = 8, NV = NS + DIM + 1;
-  static_assert(NS + 1 <= G, "one lane per Jacobian column and one for the base point");
+  constexpr int G = 32, NV = NS + DIM + 1;
+  static_assert((NS + 1) * NR <= G, "one lane per reaction of each Jacobian column and of the base point");
   const Chem<NS, NR> chem{mech};
   const int lane = threadIdx.x & (G - 1);
+  const int pt = lane / NR < NS ? lane / NR : NS;  // this lane's point: displaced along Y_pt, or the base point
+  const int rl = lane - (lane / NR) * NR;          // and its reaction
+  const int pbase = pt * NR;                       // lane of reaction 0 of the point
   const int count = *defer_count;
   const int groups = (int)(((size_t)gridDim.x * blockDim.x) / G);
   for (int g = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / G); g < count; g += groups) {
@@ -328,22 +362,39 @@ k_source_cont(const T* U, T* out, const dg_mechanism* mech, size_t plane, double
     bool nonphys = false;
     auto newton = [&](double hh) -> bool {
       for (int k_it = 0; k_it < max_iter; ++k_it) {
-        // this lane's point: Y displaced along Y_lane (lanes < NS), else Y
+        // this lane's point: Y displaced along Y_pt (pt < NS), else Y
         double Yp[NS], eps = 1.0;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
           Yp[s] = Y[s];
-          if (s == lane) {
+          if (s == pt) {
             eps = fmax(1e-7 * fabs(Y[s]), 1e-12);
             Yp[s] = Yp[s] + eps;
           }
         }
+        // the point's residual: reaction rl's rate here, the point's NR rates
+        // gathered and summed as in the one-lane residual
+        const double Tl = chem.temperature(Yp, ke, E);
+        const double Rr = chem.rate(rl, Yp, Tl);
+        double w[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) w[s] = 0.0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const double Rq = __shfl(Rr, pbase + r, G);
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+            const int dnu = mech->nu_b[r][s] - mech->nu_f[r][s];
+            if (dnu != 0) w[s] = fma(mech->kappa_r * mech->W[s] * dnu, Rq, w[s]);
+          }
+        }
         double Rl[NS];
-        const double Tl = chem.residual(Yp, Yn, hh, ke, E, Rl);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) Rl[s] = (Yp[s] - Yn[s]) - hh * w[s];
         double R0[NS];
 #pragma unroll
-        for (int s = 0; s < NS; ++s) R0[s] = __shfl(Rl[s], NS, G);
-        const double T0 = __shfl(Tl, NS, G);
+        for (int s = 0; s < NS; ++s) R0[s] = __shfl(Rl[s], NS * NR, G);
+        const double T0 = __shfl(Tl, NS * NR, G);
         if (!(T0 > 0.0)) {
           nonphys = true;
           return false;
@@ -352,9 +403,9 @@ k_source_cont(const T* U, T* out, const dg_mechanism* mech, size_t plane, double
         double J[NS][NS];
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
-          const double ek = __shfl(eps, k, G);
+          const double ek = __shfl(eps, k * NR, G);
 #pragma unroll
-          for (int s = 0; s < NS; ++s) J[s][k] = (__shfl(Rl[s], k, G) - R0[s]) / ek;
+          for (int s = 0; s < NS; ++s) J[s][k] = (__shfl(Rl[s], k * NR, G) - R0[s]) / ek;
         }
         double rhs[NS], dY[NS];
 #pragma unroll
@@ -744,8 +795,8 @@ hipError_t launch_source(const Ctx& c, const void* U, void* out, double h, int m
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  // the second pass: 32 nodes per 256-lane block, grid-stride beyond 1024 blocks
-  const int cont_blocks = (int)std::min<size_t>((total + 31) / 32, 1024);
+  // the second pass: 8 nodes per 256-lane block, grid-stride beyond 1024 blocks
+  const int cont_blocks = (int)std::min<size_t>((total + 7) / 8, 1024);
   if (c.desc.precision == DG_F32) {
     hipLaunchKernelGGL((k_source<float, 5, 5, 2>), dim3(blocks), dim3(256), 0, s, static_cast<const float*>(U),
                        static_cast<float*>(out), m, plane, c.B, h, mode, c.desc.newton_max_iter, c.desc.newton_tol,
