@@ -405,11 +405,12 @@ k_stage(StageParams sp, MeshView mv, PhysConst pc) {
 // Per direction that is 5 matrix instructions and 5 KB of permute traffic
 // per wave instead of 20 FMAs and 14.5 KB of LDS traffic (a staged flux swept
 // with D read from LDS), and no LDS tile for the flux: with U0 in LDS
-// instead of ten registers the FP64 kernel holds 76 VGPRs and runs 6 waves
+// instead of ten registers the FP64 kernel holds 74 VGPRs and runs 6 waves
 // per SIMD (86 VGPRs and 5 waves with U0 in registers and a staged flux).
 // Being one wave, the workgroup needs no barrier: LDS accesses of a wave
 // complete in order, and a wave-level fence keeps the compiler from
-// reordering them.
+// reordering them.  The LDS data of the buffer-to-LDS loads is read only
+// after an explicit wait for all of the wave's loads (wait_vmem_all).
 //
 // FP32 form: the state, U0, the output and the neighbour face nodes in LDS
 // are float, fluxes and face corrections double.  In every direction it
