@@ -440,8 +440,9 @@ __device__ __forceinline__ double lane0(double x) {
 
 // U0: whether the stage reads U0 (a != 0 in a Shu-Osher stage); without it
 // the FP64 kernel needs 3.8 KB of LDS and 72 VGPRs and runs 7 waves per SIMD
-// instead of 6.
-template <typename T, bool NT, bool U0>
+// instead of 6.  PV: a dual stage (mode 2) that reads V, with U0: V is loaded
+// into registers at entry with the other reads instead of at the output.
+template <typename T, bool NT, bool U0, bool PV>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((!std::is_same<T, float>::value && !U0) ? 7 : 4)))
 k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
   using PHYS = EulerPhys<3>;
@@ -505,6 +506,12 @@ k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
     }
   }
   constexpr bool use_u0 = U0;  // the host launches this instantiation iff mode != 0 and a != 0
+  double vr[PV ? NV : 1];       // PV: V of the dual stage, in registers from the start
+  if constexpr (PV) {
+    const rsrc_t rv = make_rsrc(static_cast<const T*>(sp.V) + (size_t)b * NV * plane, abytes);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) vr[v] = Buf<T>::template load<CP>(rv, off, v * pstride);
+  }
   if constexpr (use_u0) {  // U0 into LDS, one 4-byte load per lane and dword
     const rsrc_t r0 = make_rsrc(static_cast<const T*>(sp.U0) + (size_t)b * NV * plane, abytes);
 #pragma unroll
@@ -663,7 +670,8 @@ k_stage_n3(StageParams sp, MeshView mv, PhysConst pc) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       T w = fma(T(sp.c2), acc[v], T(sp.b2) * T(u[v]));
-      if (use_v) w = fma(T(sp.a2), T(Buf<T>::load(rv, off, v * pstride)), w);
+      if constexpr (PV) w = fma(T(sp.a2), T(vr[v]), w);
+      else if (use_v) w = fma(T(sp.a2), T(Buf<T>::load(rv, off, v * pstride)), w);
       Buf<T>::store(r2, off, w, v * pstride);
     }
   }
@@ -750,13 +758,19 @@ static hipError_t go(const Ctx& c, const StageParams& sp, hipStream_t s) {
     // displacing the neighbour faces in L2 (at cache-resident sizes it would
     // send the output past the cache the next stage reads it from)
     const size_t state_bytes = (size_t)c.B * 5 * c.E * 64 * sizeof(T);
-    const bool nt = state_bytes > NT_STATE_BYTES;
     const bool u0 = sp.mode != 0 && sp.a != 0.0;
+    // arrays the stage streams: U_k, the output, U0; the dual stage also a
+    // second output and V
+    const int arrays = 2 + (u0 ? 1 : 0) + (sp.mode == 2 ? 1 + (sp.a2 != 0.0 ? 1 : 0) : 0);
+    const bool nt = state_bytes * (sp.mode == 2 ? arrays : 1) > NT_STATE_BYTES;
+    const bool pv = u0 && sp.mode == 2 && sp.a2 != 0.0;
     const MeshView mvw = mesh_view(c);
-    if (nt && u0) hipLaunchKernelGGL((k_stage_n3<T, true, true>), dim3(nblk), dim3(64), 0, s, sp, mvw, c.pc);
-    else if (nt) hipLaunchKernelGGL((k_stage_n3<T, true, false>), dim3(nblk), dim3(64), 0, s, sp, mvw, c.pc);
-    else if (u0) hipLaunchKernelGGL((k_stage_n3<T, false, true>), dim3(nblk), dim3(64), 0, s, sp, mvw, c.pc);
-    else hipLaunchKernelGGL((k_stage_n3<T, false, false>), dim3(nblk), dim3(64), 0, s, sp, mvw, c.pc);
+    if (nt && pv) hipLaunchKernelGGL((k_stage_n3<T, true, true, true>), dim3(nblk), dim3(64), 0, s, sp, mvw, c.pc);
+    else if (nt && u0) hipLaunchKernelGGL((k_stage_n3<T, true, true, false>), dim3(nblk), dim3(64), 0, s, sp, mvw, c.pc);
+    else if (nt) hipLaunchKernelGGL((k_stage_n3<T, true, false, false>), dim3(nblk), dim3(64), 0, s, sp, mvw, c.pc);
+    else if (pv) hipLaunchKernelGGL((k_stage_n3<T, false, true, true>), dim3(nblk), dim3(64), 0, s, sp, mvw, c.pc);
+    else if (u0) hipLaunchKernelGGL((k_stage_n3<T, false, true, false>), dim3(nblk), dim3(64), 0, s, sp, mvw, c.pc);
+    else hipLaunchKernelGGL((k_stage_n3<T, false, false, false>), dim3(nblk), dim3(64), 0, s, sp, mvw, c.pc);
     return hipGetLastError();
   }
   hipLaunchKernelGGL((k_stage<DIM, N, PHYS, T, MORTAR, SPLIT>), dim3(nblk), dim3(SH::BS), 0, s, sp, mesh_view(c),
