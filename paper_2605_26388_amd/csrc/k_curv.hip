@@ -42,7 +42,11 @@ struct CurvArgs {
   double ub[5];       // conserved inflow state
 };
 
-template <int DIM, int N, bool SPLIT, typename T>
+// NT: the stage's streams (state arrays and metrics) together exceed the
+// Infinity Cache: U0 and the outputs, which no other workgroup of the stage
+// reads, then carry the non-temporal hint so that they do not displace the
+// metrics and U_k's neighbour faces
+template <int DIM, int N, bool SPLIT, typename T, bool NT = false>
 __global__ void __launch_bounds__((Shape<DIM, N>::BS)) __attribute__((amdgpu_waves_per_eu(3)))
 k_stage_curv(StageParams sp, MeshView mv, PhysConst pc, CurvArgs ca) {
   using S = Shape<DIM, N>;
@@ -109,6 +113,7 @@ k_stage_curv(StageParams sp, MeshView mv, PhysConst pc, CurvArgs ca) {
     for (int d = 0; d < DIM; ++d) Ja[l][d] = ca.met[(2 + l * DIM + d) * plane + at];
 
   const bool use_u0 = (sp.mode != 0) && (sp.a != 0.0);
+  constexpr int CP = NT ? CPOL_NT : 0;  // policy of U0 and the outputs
 
   Thermo th;
   const bool ok = PHYS::thermo(u, th, pc);
@@ -314,13 +319,13 @@ k_stage_curv(StageParams sp, MeshView mv, PhysConst pc, CurvArgs ca) {
     const rsrc_t ro = make_rsrc(static_cast<T*>(sp.out) + (size_t)b * NV * plane, abytes);
     if (sp.mode == 0) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Buf<T>::store(ro, off, acc[v], v * pstride);
+      for (int v = 0; v < NV; ++v) Buf<T>::template store<CP>(ro, off, acc[v], v * pstride);
     } else {
       double u0[NV];
       if (use_u0) {
         const rsrc_t r0 = make_rsrc(static_cast<const T*>(sp.U0) + (size_t)b * NV * plane, abytes);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) u0[v] = Buf<T>::load(r0, off, v * pstride);
+        for (int v = 0; v < NV; ++v) u0[v] = Buf<T>::template load<CP>(r0, off, v * pstride);
       }
       double r[NV];
 #pragma unroll
@@ -331,7 +336,7 @@ k_stage_curv(StageParams sp, MeshView mv, PhysConst pc, CurvArgs ca) {
       if (sp.rho_min > 0.0 || sp.p_min > 0.0)
         positivity_floor(r, sp.rho_min, sp.p_min, 1.0 / (pc.gamma - 1.0), mv.counters);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Buf<T>::store(ro, off, r[v], v * pstride);
+      for (int v = 0; v < NV; ++v) Buf<T>::template store<CP>(ro, off, r[v], v * pstride);
       if (sp.mode == 2) {  // second combination of the same L(Uk), no floor
         const rsrc_t r2 = make_rsrc(static_cast<T*>(sp.out2) + (size_t)b * NV * plane, abytes);
         const bool use_v = sp.a2 != 0.0;
@@ -339,8 +344,8 @@ k_stage_curv(StageParams sp, MeshView mv, PhysConst pc, CurvArgs ca) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           double w = fma(sp.c2, acc[v], sp.b2 * u[v]);
-          if (use_v) w = fma(sp.a2, Buf<T>::load(rv, off, v * pstride), w);
-          Buf<T>::store(r2, off, w, v * pstride);
+          if (use_v) w = fma(sp.a2, Buf<T>::template load<CP>(rv, off, v * pstride), w);
+          Buf<T>::template store<CP>(r2, off, w, v * pstride);
         }
       }
     }
@@ -351,12 +356,27 @@ template <int DIM, int N, typename T>
 static void go_curv_t(const Ctx& c, const StageParams& sp, const CurvArgs& ca, hipStream_t s) {
   using SH = Shape<DIM, N>;
   const int nEB = (c.E + SH::EPB - 1) / SH::EPB;
-  if (c.desc.volume == DG_VOLUME_SPLIT)
-    hipLaunchKernelGGL((k_stage_curv<DIM, N, true, T>), dim3(nEB * c.B), dim3(SH::BS), 0, s, sp, mesh_view(c),
-                       c.pc, ca);
-  else
-    hipLaunchKernelGGL((k_stage_curv<DIM, N, false, T>), dim3(nEB * c.B), dim3(SH::BS), 0, s, sp, mesh_view(c),
-                       c.pc, ca);
+  // bytes the stage streams: U_k, the output, U0 and the dual stage's second
+  // output and V, plus the 1/J and Ja^l planes of the metrics
+  const size_t state = (size_t)c.B * (DIM + 2) * c.E * SH::NP * sizeof(T);
+  const int arrays = 2 + (sp.mode != 0 && sp.a != 0.0 ? 1 : 0) + (sp.mode == 2 ? 1 + (sp.a2 != 0.0 ? 1 : 0) : 0);
+  const size_t metrics = (size_t)(1 + DIM * DIM) * c.E * SH::NP * sizeof(double);
+  const bool nt = DIM == 3 && N == 3 && state * arrays + metrics > ((size_t)256 << 20);  // the Infinity Cache
+  if (c.desc.volume == DG_VOLUME_SPLIT) {
+    if (nt)
+      hipLaunchKernelGGL((k_stage_curv<DIM, N, true, T, (DIM == 3 && N == 3)>), dim3(nEB * c.B), dim3(SH::BS), 0, s,
+                         sp, mesh_view(c), c.pc, ca);
+    else
+      hipLaunchKernelGGL((k_stage_curv<DIM, N, true, T>), dim3(nEB * c.B), dim3(SH::BS), 0, s, sp, mesh_view(c),
+                         c.pc, ca);
+  } else {
+    if (nt)
+      hipLaunchKernelGGL((k_stage_curv<DIM, N, false, T, (DIM == 3 && N == 3)>), dim3(nEB * c.B), dim3(SH::BS), 0,
+                         s, sp, mesh_view(c), c.pc, ca);
+    else
+      hipLaunchKernelGGL((k_stage_curv<DIM, N, false, T>), dim3(nEB * c.B), dim3(SH::BS), 0, s, sp, mesh_view(c),
+                         c.pc, ca);
+  }
 }
 
 template <int DIM, int N>
