@@ -267,7 +267,9 @@ k_adjoint(AdjParams ap, MeshView mv, PhysConst pc) {
 // Same arithmetic per term as k_adjoint (FP32 reverse step 13 % faster than
 // k_adjoint at the adjoint workload, FP64 5 %).
 // ---------------------------------------------------------------------------
-template <typename T>
+// NT: the step's streams exceed the Infinity Cache; lambda_0 and lambda_k,
+// which no other workgroup reads, carry the non-temporal hint
+template <typename T, bool NT = false>
 __global__ void __launch_bounds__(64) k_adjoint_n3(AdjParams ap, MeshView mv, PhysConst pc) {
   using PHYS = EulerPhys<3>;
   constexpr int DIM = 3, N = 3, n = 4, NP = 64, NV = 5;
@@ -336,7 +338,7 @@ __global__ void __launch_bounds__(64) k_adjoint_n3(AdjParams ap, MeshView mv, Ph
       const rsrc_t r0 = make_rsrc(static_cast<const T*>(ap.lam_0) + bo, abytes);
 #pragma unroll
       for (int v = 0; v < NV; ++v)
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(r0, DG_LDS_PTR(&sL0[v][0]), 4, off * 4u, v * pstride, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r0, DG_LDS_PTR(&sL0[v][0]), 4, off * 4u, v * pstride, 0, NT ? CPOL_NT : 0);
     }
   }
 
@@ -433,21 +435,21 @@ __global__ void __launch_bounds__(64) k_adjoint_n3(AdjParams ap, MeshView mv, Ph
   for (int v = 0; v < NV; ++v) {
     if (!read_l0) l0[v] = 0.0;
     else if constexpr (F32) l0[v] = static_cast<double>(__builtin_bit_cast(float, sL0[v][tid]));
-    else l0[v] = Buf<T>::load(make_rsrc(static_cast<const T*>(ap.lam_0) + bo, abytes), off, v * pstride);
+    else l0[v] = Buf<T>::template load<NT ? CPOL_NT : 0>(make_rsrc(static_cast<const T*>(ap.lam_0) + bo, abytes), off, v * pstride);
   }
   const rsrc_t rk = make_rsrc(static_cast<T*>(ap.lam_k) + bo, abytes);
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     double r = fma(ap.c, gout[v], ap.b * lam[v]);
     if (ap.mode == 1) r += l0[v];
-    Buf<T>::store(rk, off, r, v * pstride);
+    Buf<T>::template store<NT ? CPOL_NT : 0>(rk, off, r, v * pstride);
   }
   if (ap.mode == 0 || ap.mode == 2) {
     const rsrc_t r0 = make_rsrc(static_cast<T*>(ap.lam_0) + bo, abytes);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const double r = ap.mode == 0 ? fma(ap.a, lam[v], l0[v]) : ap.a * lam[v];
-      Buf<T>::store(r0, off, r, v * pstride);
+      Buf<T>::template store<NT ? CPOL_NT : 0>(r0, off, r, v * pstride);
     }
   }
 }
@@ -457,7 +459,12 @@ static hipError_t adj_go(const Ctx& c, const AdjParams& ap, hipStream_t s) {
   using SH = Shape<DIM, N>;
   const int nEB = (c.E + SH::EPB - 1) / SH::EPB;
   if constexpr (DIM == 3 && N == 3) {
-    hipLaunchKernelGGL((k_adjoint_n3<T>), dim3(c.E * c.B), dim3(64), 0, s, ap, mesh_view(c), c.pc);
+    // U_k, lambda_out, lambda_k and lambda_0 (read and written)
+    const size_t state = (size_t)c.B * 5 * c.E * 64 * sizeof(T);
+    if (state * 5 > ((size_t)256 << 20))  // the Infinity Cache
+      hipLaunchKernelGGL((k_adjoint_n3<T, true>), dim3(c.E * c.B), dim3(64), 0, s, ap, mesh_view(c), c.pc);
+    else
+      hipLaunchKernelGGL((k_adjoint_n3<T>), dim3(c.E * c.B), dim3(64), 0, s, ap, mesh_view(c), c.pc);
     return hipGetLastError();
   }
   hipLaunchKernelGGL((k_adjoint<DIM, N, T>), dim3(nEB * c.B), dim3(SH::BS), 0, s, ap, mesh_view(c), c.pc);
