@@ -180,3 +180,31 @@ def test_fp32_rollout_gradient_error_statement():
     err = rel_err(grads["f32"], grads["f64"])
     print(f"FP32 rollout gradient vs FP64 (16^3 N=3, batch 8, 50 steps): {err:.3e}", flush=True)
     assert err < 1e-4
+
+
+def test_adjoint_stage_full_batch_matches_single_member():
+    """The adjoint workload's reverse stage at batch 8, where the FP64
+    stage's five 84 MB streams exceed the Infinity Cache and lambda_0 and
+    lambda_k take the non-temporal policy, against the same stage of member 0
+    alone (batch 1, default policy): members do not interact and the cache
+    policy changes no arithmetic, so member 0 agrees bit for bit, in each
+    lambda_0 mode."""
+    from paper_2605_26388_amd import Solver
+    p = di.PRESETS["adjoint3d"]
+    s8 = Solver(3, 3, p["nel"], p["lo"], p["hi"], batch=p["batch"])
+    s1 = Solver(3, 3, p["nel"], p["lo"], p["hi"], batch=1)
+    X = s8.node_coords().cpu().numpy()
+    base = di.random_euler(X, p["lo"], p["hi"])
+    U = torch.tensor(np.stack([di.perturb_density(base, b) for b in range(p["batch"])])).to(s8.device).contiguous()
+    gen = torch.Generator(device="cpu").manual_seed(21)
+    lam = torch.randn(U.shape, generator=gen, dtype=torch.float64).to(s8.device)
+    l0 = torch.randn(U.shape, generator=gen, dtype=torch.float64).to(s8.device)
+    for mode in (s8.LAM0_ACCUMULATE, s8.LAM0_FOLD, s8.LAM0_INIT):
+        lk8, acc8 = s8.empty(), l0.clone()
+        s8.rk_stage_adjoint(U, lam, lk8, acc8, 0.75, 0.25, 0.01, mode)
+        lk1, acc1 = s1.empty(), l0[:1].clone()
+        s1.rk_stage_adjoint(U[:1].contiguous(), lam[:1].contiguous(), lk1, acc1, 0.75, 0.25, 0.01, mode)
+        assert torch.equal(lk8[:1], lk1), mode
+        assert torch.equal(acc8[:1], acc1), mode
+    s8.close()
+    s1.close()

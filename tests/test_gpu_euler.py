@@ -251,3 +251,44 @@ def test_vortex_run_matches_oracle():
     ex = torch.tensor(di.vortex(op.mesh.coords(), p["steps"] * dt))[None]
     got = from_gpu(op, Ug)
     assert float((got[0, 0] - ex[0, 0]).abs().max()) < 5e-2   # 8^2 elements, h = 1.25
+
+
+def _tile2(X, n16=16):
+    """A (B, nv, E, Np) state of a 16^3 mesh repeated twice along each element
+    axis (lexicographic element order, x fastest)."""
+    B, nv, _, Np = X.shape
+    Y = X.reshape(B, nv, n16, n16, n16, Np).repeat(1, 1, 2, 2, 2, 1)
+    return Y.reshape(B, nv, -1, Np).contiguous()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_dual_stage_32cubed_as_tiled_16cubed(precision):
+    """The dual stage (two combinations of one L(U_k), SSPRK54's fourth stage)
+    at 32^3, N = 3, reading V: there the FP64 stage's five 84 MB streams exceed
+    the 256 MiB Infinity Cache, so the kernel takes the non-temporal policy,
+    and V is loaded at entry.  A state that repeats a 16^3 state twice along
+    each axis, on a box twice as long (the same element sizes and arithmetic
+    per element), must give both 16^3 outputs repeated, bit for bit; the 16^3
+    outputs themselves are checked against the oracle's stage."""
+    from paper_2605_26388_amd import Solver
+    op, s16 = make_pair(3, 3, (16, 16, 16), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), precision=precision)
+    U, U0, V = (random_euler_state(op, sd) for sd in (81, 82, 83))
+    a, b, c, a2, b2, c2 = 0.4, 0.6, 0.003, 0.3, 0.5, 0.002
+    g16, g016, gv16 = to_gpu(s16, U), to_gpu(s16, U0), to_gpu(s16, V)
+    o16, w16 = s16.empty(), s16.empty()
+    s16.rk_stage_dual(g016, g16, o16, a, b, c, gv16, w16, a2, b2, c2)
+    if precision == "f64":
+        Uq = from_gpu(op, g16)
+        L = op.rhs(Uq)
+        assert rel_err(from_gpu(op, o16), a * from_gpu(op, g016) + b * Uq + c * L) < TOL64
+        assert rel_err(from_gpu(op, w16), a2 * from_gpu(op, gv16) + b2 * Uq + c2 * L) < TOL64
+    o16, w16 = o16.cpu(), w16.cpu()
+    s16.close()
+    s32 = Solver(3, 3, (32, 32, 32), (0.0, 0.0, 0.0), (2.0, 2.0, 2.0), precision=precision)
+    t = lambda X: _tile2(X.reshape(1, 5, 4096, 64)).to(s32.device, s32.dtype)
+    o32, w32 = s32.empty(), s32.empty()
+    s32.rk_stage_dual(t(U0), t(U), o32, a, b, c, t(V), w32, a2, b2, c2)
+    assert torch.equal(o32.cpu(), _tile2(o16))
+    assert torch.equal(w32.cpu(), _tile2(w16))
+    assert s32.status()["nonphysical"] == 0
+    s32.close()
